@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Throughput of the DDM structure function D(q, m) on one MI355X.
+
+One step = the whole hot path on one stack already resident in HBM:
+2-D transform of every frame, transpose to per-q time series, time-FFT
+autocorrelation + FP64 prefix sums -> D(q, m) for every kept q and every lag,
+then the azimuthal |q| average.  Default workload: 512x512 uint16 (12-bit)
+frames, N = 1024, synthetic Brownian spots (the paper-shaped case).
+
+Prints one JSON line with frames/s, the whole-path algorithmic HBM fraction, a
+roofline entry for the dominant kernel (timed live with HIP events on the
+plan's stream) and the CPU oracle timed on a bounded sample.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="paper", choices=["paper", "plain", "large"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-columns", type=int, default=64,
+                    help="kx columns of the oracle sample (all ky, all frames, all lags)")
+    ap.add_argument("--kernel-only", default=None,
+                    help="run only this many steps and nothing else (for profilers)")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(W, H, N, M, nq, pix_bytes):
+    """Bytes each kernel must move once (measurement section)."""
+    kx = W // 2 + 1
+    per = {
+        # per frame: read the frame, write its half spectrum along x
+        "row": H * W * pix_bytes + H * kx * 8,
+        # per frame: read the x-spectra, write the kept spectra to the q-major store
+        "col": H * kx * 8 + nq * 8,
+        # per wave vector: read its time series, write its D row
+        "time": N * 8 + M * 4,
+    }
+    whole = N * H * W * pix_bytes + 2 * nq * N * 8 + nq * M * 4
+    return per, whole
+
+
+def cpu_baseline(frames_cpu, ncols, nq_total):
+    import numpy as np
+    from oracle import dft, structure
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    fr = frames_cpu.numpy()
+    N, H, W = fr.shape
+    cols = list(range(ncols))
+    t0 = time.perf_counter()
+    F = dft.dft_columns(fr, cols, np.arange(H))              # [N, H, ncols]
+    Fq = F.reshape(N, -1).T.copy()                           # [H*ncols, N]
+    structure.structure_function_direct(Fq, impl="c", threads=threads)
+    dt = time.perf_counter() - t0
+    nq_s = H * ncols
+    full_s = dt * nq_total / nq_s
+    return {"value": N / full_s, "unit": "frames/s", "cores": threads, "kind": "oracle",
+            "sample": "kx columns 0..%d x all %d ky (%d of %d q), all %d frames and lags; "
+                      "%.2f s measured, extrapolated linearly in q to %.0f s" %
+                      (ncols - 1, H, nq_s, nq_total, N, dt, full_s)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the path shards over q across GPUs "
+              "but no multi-GPU run exists); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2012_05695_amd import api, synth
+
+    recipe = {"paper": synth.PAPER, "plain": synth.PLAIN, "large": synth.LARGE}[args.config]
+    W, H, N = recipe["W"], recipe["H"], recipe["N"]
+    print("bench: generating %dx%dx%d %s stack on GPU" % (W, H, N, recipe["pixel"]), file=sys.stderr,
+          flush=True)
+    frames = synth.make(recipe, device="cuda")
+    torch.cuda.synchronize()
+    plan = api.Plan(W, H, N, pixel=recipe["pixel"])
+    plan.allocate_workspace()
+    M, nq = plan.max_lag, plan.n_q
+    D = torch.empty((nq, M), dtype=torch.float32, device="cuda")
+    kx, ky = plan.q_index()
+    nbins = int((kx.astype("int64") ** 2 + ky.astype("int64") ** 2).max() ** 0.5) + 2
+    thr = api.integer_bin_thresholds(nbins)
+
+    def step():
+        plan.structure_function(frames, out=D)
+        plan.radial_average(D, thr, bin_of_q=False)
+
+    if args.kernel_only is not None:
+        for _ in range(int(args.kernel_only)):
+            step()
+        torch.cuda.synchronize()
+        print("kernel-only steps done", file=sys.stderr)
+        return
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # untimed profiling pass: which kernel dominates?
+    plan.set_profiling(["row", "col", "time", "radial"])
+    step()
+    torch.cuda.synchronize()
+    prof = {k: plan.profile(k) for k in ["row", "col", "time", "radial"]}
+    dominant = max(prof, key=lambda k: prof[k][0])
+    print("bench: per-kernel ms in one step: %s" % {k: round(v[0], 4) for k, v in prof.items()},
+          file=sys.stderr, flush=True)
+
+    # timed region: whole steps; only the dominant kernel is bracketed by events
+    plan.set_profiling([dominant])
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    k_ms, k_n = plan.profile(dominant)
+    plan.set_profiling([])
+
+    pix_bytes = 1 if recipe["pixel"] == "u8" else 2
+    per, whole = algorithmic_bytes(W, H, N, M, nq, pix_bytes)
+    units_per_launch = {"row": N, "col": N, "time": nq}[dominant] if dominant != "radial" else None
+    # launches per step of row/col split the frames into batches
+    launches_per_step = k_n / args.steps
+    if dominant in ("row", "col"):
+        bytes_per_launch = per[dominant] * N / launches_per_step
+    elif dominant == "time":
+        bytes_per_launch = per["time"] * nq / launches_per_step
+    else:
+        bytes_per_launch = nq * M * 4 / launches_per_step
+    avg_launch_ms = k_ms / k_n
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": "frames/s for D(q,dt) at 512x512x1024 (whole path incl. radial average)",
+        "value": N / (ms_step * 1e-3),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%dx%d uint16 (12-bit) x %d frames, Brownian spots, FP32 spectra, "
+                               "all %d half-plane q, all %d lags, %d integer |q| bins" %
+                               (W, H, N, nq, M, nbins),
+                   "n_q": nq, "max_lag": M},
+        "hbm_frac_whole_path": (whole / (ms_step * 1e-3) / 1e9) / HBM_PEAK_GBS,
+        "algorithmic_bytes_whole_path": whole,
+        "kernel_ms_per_step": {k: v[0] for k, v in prof.items()},
+        "roofline": {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_ms": avg_launch_ms, "launches": k_n,
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+    }
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(frames.cpu(), args.cpu_columns, nq)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,176 @@
+/*
+ * ddm.h -- C ABI of libddm: the DDM image structure function computed with a
+ * Fourier transform in time (Norouzisadeh, Cerchiari, Croccolo,
+ * arXiv 2012.05695), for AMD Instinct MI355X (gfx950).
+ *
+ * Problem statement (paper, section "The algorithm", Eq. (1)): N images I_n
+ * taken at regular time intervals; for every wave vector q of their 2-D
+ * Fourier transforms F(q, n) and every lag m (in frames),
+ *
+ *     D(q, m) = 1/(N-m) * sum_{n=m}^{N-1} |F(q, n) - F(q, n-m)|^2 .
+ *
+ * The library reaches this result without image differences: a 2-D FFT of each
+ * frame (the paper's "step one"), then per wave vector a zero-padded FFT in time,
+ * squared modulus, inverse FFT, and the squared-modulus prefix sums (Eq. (2) and
+ * Appendix B, Eqs. (B1)-(B4), the "step two").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every call returns a ddm_status and never throws or aborts across the ABI.
+ *  - Arguments are validated before anything is enqueued.  On any DDM_ERR_*
+ *    status no output buffer has been written and no work is pending;
+ *    ddm_last_error() then describes the failure (thread-local string).
+ *  - "device" pointers are HIP device memory owned by the caller (PyTorch
+ *    tensors in the Python binding).  "host" pointers are ordinary host memory,
+ *    read or written before the call returns.
+ *  - Work is enqueued asynchronously on the plan's stream; the caller
+ *    synchronises.  A plan is not thread-safe; distinct plans are independent.
+ *  - Wave-vector order ("q order"): the non-redundant half plane
+ *    kx = 0..W/2, ky = 0..H-1 (unsigned DFT index; signed frequency ky for
+ *    ky <= H/2 and ky-H above), ky-major then kx, restricted to the kept set
+ *    k2 <= k2_max where k2 = kx^2 (H/g)^2 + ky_s^2 (W/g)^2, g = gcd(W, H)
+ *    (k2 = kx^2 + ky^2 for square frames).  Real frames make F(-q) = conj F(q),
+ *    so the half plane carries every distinct D.
+ *  - Transform conventions: forward 2-D DFT with exp(-2 pi i (kx x/W + ky y/H))
+ *    and no normalisation, so D is in (pixel value)^2 * pixels^2 units.
+ */
+#ifndef DDM_H
+#define DDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DDM_ABI_VERSION 1
+
+typedef enum ddm_status {
+  DDM_OK = 0,
+  DDM_ERR_INVALID_ARGUMENT = 1, /* bad pointer, size or descriptor field */
+  DDM_ERR_UNSUPPORTED = 2,      /* valid request outside what this build implements */
+  DDM_ERR_OUT_OF_MEMORY = 3,    /* workspace missing or too small; host allocation failed */
+  DDM_ERR_HIP = 4,              /* a HIP runtime call failed (message has the HIP error) */
+  DDM_ERR_STATE = 5,            /* call on a destroyed / incomplete object */
+  DDM_WARN_FP16_SATURATED = 100 /* result written; some FP16 spectrum values saturated */
+} ddm_status;
+
+typedef enum ddm_pixel { DDM_PIX_U8 = 1, DDM_PIX_U16 = 2 } ddm_pixel;
+
+/* Storage of the per-wave-vector time series between step one and step two.
+ * F32: complex FP32.  F16_QSCALED: complex FP16 with a per-q power-of-two scale
+ * chosen from pilot frames, halving the spectrum traffic. */
+typedef enum ddm_spectrum { DDM_SPEC_F32 = 0, DDM_SPEC_F16_QSCALED = 1 } ddm_spectrum;
+
+typedef struct ddm_plan_s* ddm_plan_t;
+
+typedef struct ddm_plan_desc {
+  uint32_t struct_size;  /* = sizeof(ddm_plan_desc); guards ABI drift */
+  int32_t width;         /* W: even, 8..4096, a power of two or 3 * a power of two */
+  int32_t height;        /* H: same rules as W */
+  int32_t n_frames;      /* N >= 2 (up to 4096: time FFT length N2 <= 8192) */
+  int32_t max_lag;       /* M in [1, N]: lags 0..M-1 are produced; 0 means N */
+  int32_t pixel;         /* ddm_pixel of the frames */
+  int32_t spectrum;      /* ddm_spectrum */
+  int32_t precondition;  /* 1: transform I_t - I_0 instead of I_t (D is unchanged
+                            because D depends on frame differences only; it
+                            shrinks the dynamic range of the FP32 transforms) */
+  int32_t reserved0;
+  int64_t k2_max;        /* keep q with k2 <= k2_max (the paper's low-frequency
+                            restriction, section "Conclusion"); -1 keeps all */
+  void* stream;          /* hipStream_t for all work of this plan; NULL = default */
+} ddm_plan_desc;
+
+/* Fill a descriptor with defaults: struct_size set, max_lag 0, U16, F32,
+ * precondition 1, k2_max -1, stream NULL.  Size fields are set to 0. */
+void ddm_plan_desc_init(ddm_plan_desc* desc);
+
+/* Create a plan.  Allocates only small device tables (twiddles, row offsets;
+ * O(W + H + N) bytes).  The large buffers are the caller's: a workspace (see
+ * ddm_plan_workspace_size) and the input / output arrays.  *out is NULL on error. */
+ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out);
+
+/* Release the plan and its small tables.  NULL is accepted.  Synchronises the
+ * plan's stream first so that no enqueued kernel still reads the tables. */
+ddm_status ddm_plan_destroy(ddm_plan_t plan);
+
+/* n_q: number of kept wave vectors (rows of D).  max_lag: M.  n2: the
+ * zero-padded time-FFT length of Eq. (B4), log2 N2 = ceil(log2 N) + 1.
+ * Any output pointer may be NULL. */
+ddm_status ddm_plan_query(ddm_plan_t plan, int64_t* n_q, int32_t* max_lag, int32_t* n2);
+
+/* Host arrays of n_q entries: kx and signed ky of every row of D, in q order. */
+ddm_status ddm_plan_q_index(ddm_plan_t plan, int32_t* kx_host, int32_t* ky_signed_host);
+
+/* Workspace needed by ddm_structure_function: *full_bytes processes all wave
+ * vectors in one group; *min_bytes is the smallest workspace accepted, with
+ * which the wave vectors are processed in several groups and every frame is
+ * transformed once per group (the paper's group execution, Appendix C).
+ * Results are bit-identical for every accepted workspace size. */
+ddm_status ddm_plan_workspace_size(ddm_plan_t plan, size_t* min_bytes, size_t* full_bytes);
+
+/* Attach caller-owned device memory (at least min_bytes, 256-byte aligned).
+ * The plan keeps the pointer; the caller keeps ownership and must keep it alive
+ * while work that uses it is pending. */
+ddm_status ddm_plan_set_workspace(ddm_plan_t plan, void* workspace_dev, size_t bytes);
+
+/* The full path: frames_dev [N][H][W] (uint8 or uint16 per the plan, row-major,
+ * device) -> D_dev [n_q][M] float32 (device), D(q, m) of Eq. (1).
+ * Requires a workspace.  Returns DDM_WARN_FP16_SATURATED (result written) if
+ * the FP16 spectrum store clipped values. */
+ddm_status ddm_structure_function(ddm_plan_t plan, const void* frames_dev, float* D_dev);
+
+/* Step one only: frames_dev [N][H][W] -> spectra_dev [n_q][N] complex float32
+ * (interleaved re, im; q order, time contiguous), the 2-D transforms F(q, t)
+ * of the frames, or of I_t - I_0 when the plan preconditions.  Requires a
+ * workspace.  Used to check step one on its own. */
+ddm_status ddm_image_spectra(ddm_plan_t plan, const void* frames_dev, float* spectra_dev);
+
+/* Step two only (Appendix B): spectra_dev [n_q][N] complex float32 (as written
+ * by ddm_image_spectra, or any time series) -> D_dev [n_q][M] float32.
+ * Needs no workspace. */
+ddm_status ddm_structure_from_spectra(ddm_plan_t plan, const float* spectra_dev, float* D_dev);
+
+/* Azimuthal average of D over |q| bins (standard DDM reduction; not in the
+ * paper).  Bin b holds the kept q with T[b] <= k2 < T[b+1], T =
+ * k2_thresholds_host[0..n_bins] (strictly increasing int64, host); others are
+ * unbinned.  Weight w(q) = 2 for 0 < kx < W/2 (q stands for q and -q), else 1.
+ *   Dbar_dev [n_bins][M] float64: sum w D / sum w   (0 for an empty bin)
+ *   counts_dev [n_bins] int64:     sum w            (full-plane lattice points)
+ *   bin_of_q_dev [n_q] int32:      bin of each row of D, -1 if unbinned (may be NULL)
+ * D_dev is [n_q][M] float32 as produced by ddm_structure_function.  The sums run
+ * over q in q order in FP64, so results are deterministic. */
+ddm_status ddm_radial_average(ddm_plan_t plan, const float* D_dev, const int64_t* k2_thresholds_host,
+                              int32_t n_bins, double* Dbar_dev, int64_t* counts_dev,
+                              int32_t* bin_of_q_dev);
+
+/* Kernel kinds for profiling masks. */
+typedef enum ddm_kernel_kind {
+  DDM_KERNEL_ROW = 1,    /* row transforms of step one */
+  DDM_KERNEL_COL = 2,    /* column transforms + spectra write of step one */
+  DDM_KERNEL_TIME = 4,   /* per-wave-vector time transform of step two */
+  DDM_KERNEL_RADIAL = 8  /* radial average */
+} ddm_kernel_kind;
+
+/* Bracket every launch of the kernel kinds in kernel_mask with a pair of HIP
+ * events on the plan's stream (the paper's step-one / step-two time breakdown,
+ * its Fig. 2).  0 disables.  Resets the accumulated totals.  Host-side only. */
+ddm_status ddm_plan_set_profiling(ddm_plan_t plan, uint32_t kernel_mask);
+
+/* Total device time (ms) and launch count of one kernel kind since the last
+ * ddm_plan_set_profiling; waits for the recorded events (host sync).  One kind
+ * per call (a single ddm_kernel_kind bit). */
+ddm_status ddm_plan_get_profile(ddm_plan_t plan, uint32_t kernel_kind, double* total_ms,
+                                int64_t* launches);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* ddm_last_error(void);
+
+/* Library ABI version (DDM_ABI_VERSION of the build). */
+int32_t ddm_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDM_H */

@@ -1,0 +1,96 @@
+"""ctypes loader for libddm.so: declarations mirror include/ddm.h one to one.
+
+The library is built in-tree (``python -m paper_2012_05695_amd.build``).  There
+is no fallback: if the shared object is missing or fails to load, importing
+the binding raises.
+"""
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libddm.so")
+
+c_int32 = ctypes.c_int32
+c_int64 = ctypes.c_int64
+c_uint32 = ctypes.c_uint32
+c_size_t = ctypes.c_size_t
+c_void_p = ctypes.c_void_p
+P = ctypes.POINTER
+
+DDM_OK = 0
+DDM_ERR_INVALID_ARGUMENT = 1
+DDM_ERR_UNSUPPORTED = 2
+DDM_ERR_OUT_OF_MEMORY = 3
+DDM_ERR_HIP = 4
+DDM_ERR_STATE = 5
+DDM_WARN_FP16_SATURATED = 100
+
+DDM_KERNEL_ROW = 1
+DDM_KERNEL_COL = 2
+DDM_KERNEL_TIME = 4
+DDM_KERNEL_RADIAL = 8
+
+DDM_PIX_U8 = 1
+DDM_PIX_U16 = 2
+DDM_SPEC_F32 = 0
+DDM_SPEC_F16_QSCALED = 1
+
+STATUS_NAMES = {
+    0: "DDM_OK",
+    1: "DDM_ERR_INVALID_ARGUMENT",
+    2: "DDM_ERR_UNSUPPORTED",
+    3: "DDM_ERR_OUT_OF_MEMORY",
+    4: "DDM_ERR_HIP",
+    5: "DDM_ERR_STATE",
+    100: "DDM_WARN_FP16_SATURATED",
+}
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", c_uint32),
+        ("width", c_int32),
+        ("height", c_int32),
+        ("n_frames", c_int32),
+        ("max_lag", c_int32),
+        ("pixel", c_int32),
+        ("spectrum", c_int32),
+        ("precondition", c_int32),
+        ("reserved0", c_int32),
+        ("k2_max", c_int64),
+        ("stream", c_void_p),
+    ]
+
+
+# (name, restype, argtypes) for every symbol of include/ddm.h
+SIGNATURES = [
+    ("ddm_plan_desc_init", None, [P(PlanDesc)]),
+    ("ddm_plan_create", c_int32, [P(PlanDesc), P(c_void_p)]),
+    ("ddm_plan_destroy", c_int32, [c_void_p]),
+    ("ddm_plan_query", c_int32, [c_void_p, P(c_int64), P(c_int32), P(c_int32)]),
+    ("ddm_plan_q_index", c_int32, [c_void_p, c_void_p, c_void_p]),
+    ("ddm_plan_workspace_size", c_int32, [c_void_p, P(c_size_t), P(c_size_t)]),
+    ("ddm_plan_set_workspace", c_int32, [c_void_p, c_void_p, c_size_t]),
+    ("ddm_structure_function", c_int32, [c_void_p, c_void_p, c_void_p]),
+    ("ddm_image_spectra", c_int32, [c_void_p, c_void_p, c_void_p]),
+    ("ddm_structure_from_spectra", c_int32, [c_void_p, c_void_p, c_void_p]),
+    ("ddm_radial_average", c_int32,
+     [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    ("ddm_plan_set_profiling", c_int32, [c_void_p, c_uint32]),
+    ("ddm_plan_get_profile", c_int32, [c_void_p, c_uint32, P(ctypes.c_double), P(c_int64)]),
+    ("ddm_last_error", ctypes.c_char_p, []),
+    ("ddm_abi_version", c_int32, []),
+]
+
+
+def load(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(
+            "libddm.so not found at %s; build it with `python -m paper_2012_05695_amd.build`" % path)
+    lib = ctypes.CDLL(path)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib

@@ -1,0 +1,250 @@
+"""Python binding of libddm (argument marshalling only).
+
+Every computation runs in the HIP kernels behind the C ABI of
+``include/ddm.h``; this module checks tensor shapes and dtypes, passes device
+pointers and the current HIP stream, and turns status codes into exceptions.
+PyTorch provides device memory and streams.
+"""
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_lib = L.load()
+
+
+class DdmError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (L.STATUS_NAMES.get(status, str(status)), message))
+        self.status = status
+
+
+def _check(st):
+    if st == L.DDM_OK:
+        return st
+    if st == L.DDM_WARN_FP16_SATURATED:
+        return st
+    raise DdmError(st, (_lib.ddm_last_error() or b"").decode())
+
+
+def last_error():
+    return (_lib.ddm_last_error() or b"").decode()
+
+
+def abi_version():
+    return int(_lib.ddm_abi_version())
+
+
+_PIX = {"u8": L.DDM_PIX_U8, "u16": L.DDM_PIX_U16}
+_PIX_DTYPES = {L.DDM_PIX_U8: (torch.uint8,), L.DDM_PIX_U16: (torch.uint16, torch.int16)}
+_SPEC = {"f32": L.DDM_SPEC_F32, "f16": L.DDM_SPEC_F16_QSCALED}
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _require(t, name, dtypes, shape, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if t.device.type != "cuda":
+        raise ValueError("%s must be on a HIP device (got %s)" % (name, t.device))
+    if device is not None and t.device.index != device:
+        raise ValueError("%s is on device %s, plan on cuda:%d" % (name, t.device, device))
+    if t.dtype not in dtypes:
+        raise TypeError("%s dtype %s, expected one of %s" % (name, t.dtype, dtypes))
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+class Plan:
+    """A structure-function plan for W x H frames, N per stack.
+
+    Mirrors ``ddm_plan_create``; see include/ddm.h for the meaning of each field.
+    """
+
+    def __init__(self, width, height, n_frames, max_lag=0, pixel="u16", spectrum="f32",
+                 precondition=True, k2_max=-1, stream=None, device=None):
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        self.width, self.height, self.n_frames = int(width), int(height), int(n_frames)
+        self.pixel = _PIX[pixel] if isinstance(pixel, str) else int(pixel)
+        self._stream = stream
+        d = L.PlanDesc()
+        _lib.ddm_plan_desc_init(ctypes.byref(d))
+        d.width, d.height, d.n_frames = self.width, self.height, self.n_frames
+        d.max_lag = int(max_lag)
+        d.pixel = self.pixel
+        d.spectrum = _SPEC[spectrum] if isinstance(spectrum, str) else int(spectrum)
+        d.precondition = 1 if precondition else 0
+        d.k2_max = int(k2_max)
+        with torch.cuda.device(self.device):
+            d.stream = _stream_handle(stream).value
+        self._desc = d
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.ddm_plan_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        nq, ml, n2 = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.ddm_plan_query(h, ctypes.byref(nq), ctypes.byref(ml), ctypes.byref(n2)))
+        self.n_q, self.max_lag, self.n2 = int(nq.value), int(ml.value), int(n2.value)
+        self._ws = None
+
+    # -- lifetime --
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            with torch.cuda.device(self.device):
+                _check(_lib.ddm_plan_destroy(self._h))
+            self._h = ctypes.c_void_p()
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- queries --
+    def q_index(self):
+        kx = np.empty(self.n_q, dtype=np.int32)
+        ky = np.empty(self.n_q, dtype=np.int32)
+        _check(_lib.ddm_plan_q_index(self._h, kx.ctypes.data, ky.ctypes.data))
+        return kx, ky
+
+    def workspace_size(self):
+        mn, full = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(_lib.ddm_plan_workspace_size(self._h, ctypes.byref(mn), ctypes.byref(full)))
+        return int(mn.value), int(full.value)
+
+    def set_workspace(self, ws):
+        _require(ws, "workspace", (torch.uint8,), (ws.numel(),), self.device)
+        _check(_lib.ddm_plan_set_workspace(self._h, ctypes.c_void_p(ws.data_ptr()), ws.numel()))
+        self._ws = ws
+
+    def allocate_workspace(self, nbytes=None):
+        mn, full = self.workspace_size()
+        n = full if nbytes is None else max(int(nbytes), mn)
+        ws = torch.empty(n, dtype=torch.uint8, device="cuda:%d" % self.device)
+        self.set_workspace(ws)
+        return ws
+
+    # -- profiling (event pairs around launches on the plan's stream) --
+    KERNELS = {"row": L.DDM_KERNEL_ROW, "col": L.DDM_KERNEL_COL, "time": L.DDM_KERNEL_TIME,
+               "radial": L.DDM_KERNEL_RADIAL}
+
+    def set_profiling(self, kinds=()):
+        mask = 0
+        for k in kinds:
+            mask |= self.KERNELS[k]
+        _check(_lib.ddm_plan_set_profiling(self._h, mask))
+
+    def profile(self, kind):
+        """(total device ms, launches) of one kernel kind since set_profiling."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(_lib.ddm_plan_get_profile(self._h, self.KERNELS[kind], ctypes.byref(ms), ctypes.byref(n)))
+        return float(ms.value), int(n.value)
+
+    # -- computations --
+    def _frames_ok(self, frames):
+        _require(frames, "frames", _PIX_DTYPES[self.pixel],
+                 (self.n_frames, self.height, self.width), self.device)
+
+    def structure_function(self, frames, out=None):
+        """D [n_q, max_lag] float32 of frames [N, H, W] (device tensors)."""
+        self._frames_ok(frames)
+        if self._ws is None:
+            self.allocate_workspace()
+        if out is None:
+            out = torch.empty((self.n_q, self.max_lag), dtype=torch.float32, device=frames.device)
+        _require(out, "D", (torch.float32,), (self.n_q, self.max_lag), self.device)
+        with torch.cuda.device(self.device):
+            _check(_lib.ddm_structure_function(self._h, ctypes.c_void_p(frames.data_ptr()),
+                                               ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def image_spectra(self, frames, out=None):
+        """F [n_q, N] complex64: step one only (frame 0 subtracted if the plan preconditions)."""
+        self._frames_ok(frames)
+        if self._ws is None:
+            self.allocate_workspace()
+        if out is None:
+            out = torch.empty((self.n_q, self.n_frames), dtype=torch.complex64, device=frames.device)
+        _require(out, "spectra", (torch.complex64,), (self.n_q, self.n_frames), self.device)
+        with torch.cuda.device(self.device):
+            _check(_lib.ddm_image_spectra(self._h, ctypes.c_void_p(frames.data_ptr()),
+                                          ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def structure_from_spectra(self, spectra, out=None):
+        """D [n_q, max_lag] float32 from time series [n_q, N] complex64: step two only."""
+        _require(spectra, "spectra", (torch.complex64,), (self.n_q, self.n_frames), self.device)
+        if out is None:
+            out = torch.empty((self.n_q, self.max_lag), dtype=torch.float32, device=spectra.device)
+        _require(out, "D", (torch.float32,), (self.n_q, self.max_lag), self.device)
+        with torch.cuda.device(self.device):
+            _check(_lib.ddm_structure_from_spectra(self._h, ctypes.c_void_p(spectra.data_ptr()),
+                                                   ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def radial_average(self, D, thresholds, bin_of_q=True):
+        """(Dbar [n_bins, M] float64, counts [n_bins] int64, bin_of_q [n_q] int32 or None)."""
+        _require(D, "D", (torch.float32,), (self.n_q, self.max_lag), self.device)
+        thr = np.ascontiguousarray(np.asarray(thresholds, dtype=np.int64))
+        nb = len(thr) - 1
+        if nb < 0:
+            raise ValueError("thresholds needs at least one entry")
+        dev = D.device
+        Dbar = torch.empty((max(nb, 0), self.max_lag), dtype=torch.float64, device=dev)
+        counts = torch.empty((max(nb, 0),), dtype=torch.int64, device=dev)
+        boq = torch.empty((self.n_q,), dtype=torch.int32, device=dev) if bin_of_q else None
+        with torch.cuda.device(self.device):
+            _check(_lib.ddm_radial_average(
+                self._h, ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(thr.ctypes.data), nb,
+                ctypes.c_void_p(Dbar.data_ptr()), ctypes.c_void_p(counts.data_ptr()),
+                ctypes.c_void_p(boq.data_ptr() if boq is not None else 0)))
+        return Dbar, counts, boq
+
+
+def integer_bin_thresholds(n_bins):
+    """Thresholds of the bins b = round(|k|), b = 0..n_bins-1, on integer k2.
+
+    round(sqrt(k2)) = b  <=>  b^2 - b + 1 <= k2 <= b^2 + b, so T_0 = 0 and
+    T_b = b^2 - b + 1.
+    """
+    b = np.arange(n_bins + 1, dtype=np.int64)
+    t = b * b - b + 1
+    t[0] = 0
+    return t
+
+
+def log_bin_thresholds(n_bins, k_min, k_max):
+    """n_bins logarithmic |k| bins with edges geomspace(k_min, k_max, n_bins+1).
+
+    Each edge e becomes the integer threshold ceil(e^2) on k2 (so that
+    k2 >= T <=> |k| >= e for integer k2, with e^2 evaluated in FP64); repeated
+    thresholds are not allowed, so the low edges must be far enough apart.
+    """
+    e = np.geomspace(float(k_min), float(k_max), int(n_bins) + 1)
+    t = np.ceil(e * e).astype(np.int64)
+    t[-1] = max(t[-1], int(np.floor(k_max * k_max)) + 1)
+    if np.any(np.diff(t) <= 0):
+        raise ValueError("log bins collapse at low k; raise k_min or lower n_bins")
+    return t

@@ -1,0 +1,493 @@
+// C ABI of libddm: plans, validation, workspace partition and the launch
+// sequence of the structure-function path.  No exception crosses the ABI;
+// every entry point returns a ddm_status and records a thread-local message.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace ddm;
+
+namespace {
+
+thread_local std::string g_err;
+
+ddm_status fail(ddm_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+ddm_status hip_fail(hipError_t e, const char* what) {
+  return fail(DDM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+constexpr size_t kInterTargetBytes = 64u << 20;  // row-transform intermediate per batch
+
+}  // namespace
+
+struct ddm_plan_s {
+  uint32_t magic;
+  ddm_plan_desc d;
+  int W, H, N, M;
+  int L;         // time transform length (N2 / 2), >= 16
+  int n2_paper;  // Eq. (B4) length
+  int64_t nq;
+  int64_t ca, cc;  // k2 = kx^2 ca + ky_s^2 cc
+  std::vector<int32_t> qoff, kxcnt;
+  int kx_needed, cw, kxw, ncol_tiles;
+  size_t frame_inter_bytes;
+  int fb_target;
+  hipStream_t stream;
+  // device tables (one allocation)
+  void* dev_tables;
+  float2 *twW, *twH, *twT;
+  int32_t *qoff_d, *kxcnt_d;
+  // radial thresholds (grown on demand)
+  int64_t* thr_d;
+  size_t thr_cap;
+  // workspace
+  void* ws;
+  size_t ws_bytes;
+  // profiling: event pairs around launches of the kinds in prof_mask
+  uint32_t prof_mask;
+  struct Rec { uint32_t kind; hipEvent_t a, b; };
+  std::vector<Rec> prof_recs;
+  double prof_ms[4];
+  int64_t prof_n[4];
+};
+
+static int kind_slot(uint32_t kind) {
+  switch (kind) {
+    case DDM_KERNEL_ROW: return 0;
+    case DDM_KERNEL_COL: return 1;
+    case DDM_KERNEL_TIME: return 2;
+    case DDM_KERNEL_RADIAL: return 3;
+    default: return -1;
+  }
+}
+
+// Collect finished event pairs into the per-kind totals (waits for them).
+static hipError_t prof_drain(ddm_plan_s* p) {
+  hipError_t err = hipSuccess;
+  for (auto& r : p->prof_recs) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e == hipSuccess) {
+      const int s = kind_slot(r.kind);
+      p->prof_ms[s] += ms;
+      p->prof_n[s] += 1;
+    } else if (err == hipSuccess) {
+      err = e;
+    }
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  p->prof_recs.clear();
+  return err;
+}
+
+// RAII bracket: records an event pair around one launch when profiled.
+struct ProfScope {
+  ddm_plan_s* p;
+  uint32_t kind;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(ddm_plan_s* p_, uint32_t k) : p(p_), kind(k) {
+    if (p->prof_mask & kind) {
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        a = b = nullptr;
+        return;
+      }
+      hipEventRecord(a, p->stream);
+    }
+  }
+  ~ProfScope() {
+    if (a != nullptr) {
+      hipEventRecord(b, p->stream);
+      p->prof_recs.push_back({kind, a, b});
+    }
+  }
+};
+
+static constexpr uint32_t kPlanMagic = 0x44444d31u;  // "DDM1"
+
+static ddm_status check_plan(ddm_plan_t p) {
+  if (p == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (p->magic != kPlanMagic) return fail(DDM_ERR_STATE, "plan handle is not a live plan");
+  return DDM_OK;
+}
+
+static void fill_twiddles(std::vector<float2>& h, size_t off, int L) {
+  // tw[j] = exp(-2 pi i j / L), evaluated in FP64, rounded once to FP32
+  for (int j = 0; j < L; ++j) {
+    const double a = 2.0 * M_PI * (double)j / (double)L;
+    h[off + j] = make_float2((float)std::cos(a), (float)-std::sin(a));
+  }
+}
+
+extern "C" {
+
+void ddm_plan_desc_init(ddm_plan_desc* d) {
+  if (d == nullptr) return;
+  std::memset(d, 0, sizeof(*d));
+  d->struct_size = sizeof(ddm_plan_desc);
+  d->max_lag = 0;
+  d->pixel = DDM_PIX_U16;
+  d->spectrum = DDM_SPEC_F32;
+  d->precondition = 1;
+  d->k2_max = -1;
+  d->stream = nullptr;
+}
+
+int32_t ddm_abi_version(void) { return DDM_ABI_VERSION; }
+
+const char* ddm_last_error(void) { return g_err.c_str(); }
+
+ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
+  if (out == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (desc == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "desc is NULL");
+  if (desc->struct_size != sizeof(ddm_plan_desc))
+    return fail(DDM_ERR_INVALID_ARGUMENT, "desc.struct_size %u != %zu (header/library mismatch)",
+                desc->struct_size, sizeof(ddm_plan_desc));
+  const int W = desc->width, H = desc->height, N = desc->n_frames;
+  if (W <= 0 || H <= 0) return fail(DDM_ERR_INVALID_ARGUMENT, "width/height must be positive");
+  if (!supported_spatial(W) || !supported_spatial(H))
+    return fail(DDM_ERR_UNSUPPORTED,
+                "frame %dx%d: each side must be 2^k (16..4096) or 3*2^k (48..3072)", W, H);
+  if (N < 2) return fail(DDM_ERR_INVALID_ARGUMENT, "n_frames must be >= 2");
+  if (N > 4096) return fail(DDM_ERR_UNSUPPORTED, "n_frames > 4096 (time FFT length > 8192)");
+  if (desc->max_lag < 0 || desc->max_lag > N)
+    return fail(DDM_ERR_INVALID_ARGUMENT, "max_lag must be in [0, n_frames]");
+  if (desc->pixel != DDM_PIX_U8 && desc->pixel != DDM_PIX_U16)
+    return fail(DDM_ERR_INVALID_ARGUMENT, "pixel must be DDM_PIX_U8 or DDM_PIX_U16");
+  if (desc->spectrum != DDM_SPEC_F32 && desc->spectrum != DDM_SPEC_F16_QSCALED)
+    return fail(DDM_ERR_INVALID_ARGUMENT, "unknown spectrum storage %d", desc->spectrum);
+  if (desc->spectrum == DDM_SPEC_F16_QSCALED)
+    return fail(DDM_ERR_UNSUPPORTED, "FP16 spectrum store is not available in this build");
+  if (desc->precondition != 0 && desc->precondition != 1)
+    return fail(DDM_ERR_INVALID_ARGUMENT, "precondition must be 0 or 1");
+  if (desc->k2_max < -1) return fail(DDM_ERR_INVALID_ARGUMENT, "k2_max must be >= -1");
+
+  ddm_plan_s* p = new (std::nothrow) ddm_plan_s();
+  if (p == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  p->magic = kPlanMagic;
+  p->d = *desc;
+  p->W = W;
+  p->H = H;
+  p->N = N;
+  p->M = desc->max_lag == 0 ? N : desc->max_lag;
+  int l = 1;
+  while (l < N) l <<= 1;
+  p->n2_paper = 2 * l;
+  p->L = std::max(16, l);
+  const int64_t g = std::gcd(W, H);
+  p->ca = (int64_t)(H / g) * (H / g);
+  p->cc = (int64_t)(W / g) * (W / g);
+  p->qoff.assign(H, 0);
+  p->kxcnt.assign(H, 0);
+  int64_t nq = 0;
+  int kxn = 0;
+  for (int ky = 0; ky < H; ++ky) {
+    const int64_t kys = ky <= H / 2 ? ky : ky - H;
+    int cnt = 0;
+    for (int kx = 0; kx <= W / 2; ++kx) {
+      const int64_t k2 = (int64_t)kx * kx * p->ca + kys * kys * p->cc;
+      if (desc->k2_max >= 0 && k2 > desc->k2_max) break;  // k2 grows with kx
+      ++cnt;
+    }
+    p->qoff[ky] = (int32_t)nq;
+    p->kxcnt[ky] = cnt;
+    nq += cnt;
+    kxn = std::max(kxn, cnt);
+  }
+  p->nq = nq;
+  p->kx_needed = kxn;
+  const ColCfg cc = col_cfg(H);
+  p->cw = cc.cw;
+  p->ncol_tiles = (kxn + p->cw - 1) / p->cw;
+  p->kxw = p->ncol_tiles * p->cw;
+  p->frame_inter_bytes = (size_t)H * p->kxw * sizeof(float2);
+  p->fb_target = (int)std::max<size_t>(1, std::min<size_t>(N, kInterTargetBytes / p->frame_inter_bytes));
+  p->stream = (hipStream_t)desc->stream;
+
+  // device tables: twiddles for W, H, 2L; q offsets and counts per ky row
+  const size_t ntw = (size_t)W + H + 2 * (size_t)p->L;
+  std::vector<float2> tw(ntw);
+  fill_twiddles(tw, 0, W);
+  fill_twiddles(tw, W, H);
+  fill_twiddles(tw, W + H, 2 * p->L);
+  const size_t tw_bytes = align256(ntw * sizeof(float2));
+  const size_t tab_bytes = tw_bytes + 2 * align256(H * sizeof(int32_t));
+  hipError_t e = hipMalloc(&p->dev_tables, tab_bytes);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipMalloc(plan tables)");
+  }
+  char* base = (char*)p->dev_tables;
+  p->twW = (float2*)base;
+  p->twH = p->twW + W;
+  p->twT = p->twH + H;
+  p->qoff_d = (int32_t*)(base + tw_bytes);
+  p->kxcnt_d = (int32_t*)(base + tw_bytes + align256(H * sizeof(int32_t)));
+  if ((e = hipMemcpy(p->twW, tw.data(), ntw * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(p->qoff_d, p->qoff.data(), H * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(p->kxcnt_d, p->kxcnt.data(), H * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess) {
+    hipFree(p->dev_tables);
+    delete p;
+    return hip_fail(e, "hipMemcpy(plan tables)");
+  }
+  p->thr_d = nullptr;
+  p->thr_cap = 0;
+  p->ws = nullptr;
+  p->ws_bytes = 0;
+  p->prof_mask = 0;
+  for (int i = 0; i < 4; ++i) {
+    p->prof_ms[i] = 0.0;
+    p->prof_n[i] = 0;
+  }
+  *out = p;
+  g_err.clear();
+  return DDM_OK;
+}
+
+ddm_status ddm_plan_destroy(ddm_plan_t p) {
+  if (p == nullptr) return DDM_OK;
+  if (p->magic != kPlanMagic) return fail(DDM_ERR_STATE, "plan handle is not a live plan");
+  hipStreamSynchronize(p->stream);
+  prof_drain(p);
+  p->magic = 0;
+  if (p->dev_tables) hipFree(p->dev_tables);
+  if (p->thr_d) hipFree(p->thr_d);
+  delete p;
+  return DDM_OK;
+}
+
+ddm_status ddm_plan_query(ddm_plan_t p, int64_t* n_q, int32_t* max_lag, int32_t* n2) {
+  ddm_status st = check_plan(p);
+  if (st != DDM_OK) return st;
+  if (n_q) *n_q = p->nq;
+  if (max_lag) *max_lag = p->M;
+  if (n2) *n2 = p->n2_paper;
+  return DDM_OK;
+}
+
+ddm_status ddm_plan_q_index(ddm_plan_t p, int32_t* kx_host, int32_t* ky_signed_host) {
+  ddm_status st = check_plan(p);
+  if (st != DDM_OK) return st;
+  if (kx_host == nullptr || ky_signed_host == nullptr)
+    return fail(DDM_ERR_INVALID_ARGUMENT, "output arrays must be non-NULL");
+  for (int ky = 0; ky < p->H; ++ky) {
+    const int kys = ky <= p->H / 2 ? ky : ky - p->H;
+    for (int kx = 0; kx < p->kxcnt[ky]; ++kx) {
+      kx_host[p->qoff[ky] + kx] = kx;
+      ky_signed_host[p->qoff[ky] + kx] = kys;
+    }
+  }
+  return DDM_OK;
+}
+
+static size_t spec_block_bytes(const ddm_plan_s* p) { return (size_t)p->N * kSpecQB * sizeof(float2); }
+static int64_t n_spec_blocks(const ddm_plan_s* p) { return (p->nq + kSpecQB - 1) / kSpecQB; }
+
+ddm_status ddm_plan_workspace_size(ddm_plan_t p, size_t* min_bytes, size_t* full_bytes) {
+  ddm_status st = check_plan(p);
+  if (st != DDM_OK) return st;
+  const size_t fib = align256(p->frame_inter_bytes);
+  if (full_bytes) *full_bytes = align256((size_t)p->fb_target * p->frame_inter_bytes) +
+                                (size_t)n_spec_blocks(p) * spec_block_bytes(p);
+  if (min_bytes) *min_bytes = fib + spec_block_bytes(p);
+  return DDM_OK;
+}
+
+ddm_status ddm_plan_set_workspace(ddm_plan_t p, void* ws, size_t bytes) {
+  ddm_status st = check_plan(p);
+  if (st != DDM_OK) return st;
+  size_t mn = 0;
+  ddm_plan_workspace_size(p, &mn, nullptr);
+  if (ws == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (((uintptr_t)ws & 255) != 0) return fail(DDM_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+  if (bytes < mn) return fail(DDM_ERR_OUT_OF_MEMORY, "workspace %zu bytes < minimum %zu", bytes, mn);
+  p->ws = ws;
+  p->ws_bytes = bytes;
+  return DDM_OK;
+}
+
+// Split the workspace into the row intermediate (fb frames) and the spectra
+// store of one group (gblocks q-blocks).
+static void partition(const ddm_plan_s* p, int* fb, int64_t* gblocks) {
+  const size_t blk = spec_block_bytes(p);
+  const int64_t nb = n_spec_blocks(p);
+  const size_t fib = p->frame_inter_bytes;
+  const size_t all_spec = (size_t)nb * blk;
+  int f;
+  int64_t g;
+  if (p->ws_bytes >= all_spec + align256(fib)) {
+    g = nb;
+    size_t room = p->ws_bytes - all_spec;
+    f = (int)std::min<size_t>(p->fb_target, std::max<size_t>(1, room / fib));
+    while (f > 1 && align256((size_t)f * fib) > room) --f;
+  } else {
+    f = (int)std::min<size_t>(p->fb_target, std::max<size_t>(1, (p->ws_bytes / 8) / fib));
+    g = (int64_t)((p->ws_bytes - align256((size_t)f * fib)) / blk);
+    if (g < 1) {
+      f = 1;
+      g = (int64_t)((p->ws_bytes - align256(fib)) / blk);
+    }
+  }
+  *fb = f;
+  *gblocks = g;
+}
+
+// Step one for frames [0, N) into the spectra of q in [q_lo, q_hi).
+static ddm_status run_step_one(ddm_plan_s* p, const void* frames, float2* inter, int fb, int64_t q_lo,
+                               int64_t q_hi, int qb, float2* spec) {
+  QTable qt{p->qoff_d, p->kxcnt_d};
+  for (int t0 = 0; t0 < p->N; t0 += fb) {
+    const int nf = std::min(fb, p->N - t0);
+    hipError_t e;
+    {
+      ProfScope ps(p, DDM_KERNEL_ROW);
+      e = launch_row(p->stream, p->d.pixel, frames, p->W, p->H, t0, nf, p->d.precondition,
+                              inter, p->kxw, p->twW, 1);
+    }
+    if (e != hipSuccess) return hip_fail(e, "row transform launch");
+    {
+      ProfScope ps(p, DDM_KERNEL_COL);
+      e = launch_col(p->stream, inter, p->H, p->kxw, p->ncol_tiles, t0, nf, p->N, qt, q_lo, q_hi, qb,
+                     spec, p->twH, 1);
+    }
+    if (e != hipSuccess) return hip_fail(e, "column transform launch");
+  }
+  return DDM_OK;
+}
+
+ddm_status ddm_structure_function(ddm_plan_t p, const void* frames, float* D) {
+  ddm_status st = check_plan(p);
+  if (st != DDM_OK) return st;
+  if (frames == nullptr || D == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "frames/D is NULL");
+  if (p->ws == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "no workspace attached (ddm_plan_set_workspace)");
+  int fb;
+  int64_t gblocks;
+  partition(p, &fb, &gblocks);
+  float2* inter = (float2*)p->ws;
+  float2* spec = (float2*)((char*)p->ws + align256((size_t)fb * p->frame_inter_bytes));
+  const int64_t gq = gblocks * kSpecQB;
+  for (int64_t q_lo = 0; q_lo < p->nq; q_lo += gq) {
+    const int64_t q_hi = std::min(p->nq, q_lo + gq);
+    st = run_step_one(p, frames, inter, fb, q_lo, q_hi, kSpecQB, spec);
+    if (st != DDM_OK) return st;
+    hipError_t e;
+    {
+      ProfScope ps(p, DDM_KERNEL_TIME);
+      e = launch_time(p->stream, spec, kSpecQB, q_hi - q_lo, p->N, p->M, p->twT,
+                      D + (size_t)q_lo * p->M);
+    }
+    if (e != hipSuccess) return hip_fail(e, "time transform launch");
+  }
+  return DDM_OK;
+}
+
+ddm_status ddm_image_spectra(ddm_plan_t p, const void* frames, float* spectra) {
+  ddm_status st = check_plan(p);
+  if (st != DDM_OK) return st;
+  if (frames == nullptr || spectra == nullptr)
+    return fail(DDM_ERR_INVALID_ARGUMENT, "frames/spectra is NULL");
+  if (p->ws == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "no workspace attached (ddm_plan_set_workspace)");
+  const size_t fib = p->frame_inter_bytes;
+  int fb = (int)std::min<size_t>(p->fb_target, std::max<size_t>(1, p->ws_bytes / fib));
+  while (fb > 1 && (size_t)fb * fib > p->ws_bytes) --fb;
+  return run_step_one(p, frames, (float2*)p->ws, fb, 0, p->nq, 1, (float2*)spectra);
+}
+
+ddm_status ddm_structure_from_spectra(ddm_plan_t p, const float* spectra, float* D) {
+  ddm_status st = check_plan(p);
+  if (st != DDM_OK) return st;
+  if (spectra == nullptr || D == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "spectra/D is NULL");
+  hipError_t e;
+  {
+    ProfScope ps(p, DDM_KERNEL_TIME);
+    e = launch_time(p->stream, (const float2*)spectra, 1, p->nq, p->N, p->M, p->twT, D);
+  }
+  if (e != hipSuccess) return hip_fail(e, "time transform launch");
+  return DDM_OK;
+}
+
+ddm_status ddm_radial_average(ddm_plan_t p, const float* D, const int64_t* thr, int32_t n_bins,
+                              double* Dbar, int64_t* counts, int32_t* bin_of_q) {
+  ddm_status st = check_plan(p);
+  if (st != DDM_OK) return st;
+  if (n_bins < 0) return fail(DDM_ERR_INVALID_ARGUMENT, "n_bins must be >= 0");
+  if (D == nullptr || thr == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "D/thresholds is NULL");
+  if (n_bins > 0 && (Dbar == nullptr || counts == nullptr))
+    return fail(DDM_ERR_INVALID_ARGUMENT, "Dbar/counts is NULL");
+  if (thr[0] < 0) return fail(DDM_ERR_INVALID_ARGUMENT, "thresholds must be >= 0");
+  for (int b = 0; b < n_bins; ++b)
+    if (thr[b + 1] <= thr[b])
+      return fail(DDM_ERR_INVALID_ARGUMENT, "thresholds must be strictly increasing (at %d)", b);
+  const size_t need = (size_t)(n_bins + 1) * sizeof(int64_t);
+  if (need > p->thr_cap) {
+    hipError_t e = hipStreamSynchronize(p->stream);  // the old buffer may still be read
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (p->thr_d) hipFree(p->thr_d);
+    p->thr_d = nullptr;
+    p->thr_cap = 0;
+    e = hipMalloc(&p->thr_d, need);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(thresholds)");
+    p->thr_cap = need;
+  }
+  hipError_t e = hipMemcpyAsync(p->thr_d, thr, need, hipMemcpyHostToDevice, p->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(thresholds)");
+  e = hipStreamSynchronize(p->stream);  // the host array may be released after return
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  QTable qt{p->qoff_d, p->kxcnt_d};
+  ProfScope ps(p, DDM_KERNEL_RADIAL);
+  e = launch_radial(p->stream, D, p->nq, p->M, p->W, p->H, p->ca, p->cc, qt, p->thr_d, n_bins, Dbar,
+                    counts, bin_of_q);
+  if (e != hipSuccess) return hip_fail(e, "radial average launch");
+  return DDM_OK;
+}
+
+ddm_status ddm_plan_set_profiling(ddm_plan_t p, uint32_t mask) {
+  ddm_status st = check_plan(p);
+  if (st != DDM_OK) return st;
+  if (mask & ~15u) return fail(DDM_ERR_INVALID_ARGUMENT, "unknown kernel kind bits in mask 0x%x", mask);
+  hipError_t e = prof_drain(p);
+  p->prof_mask = mask;
+  for (int i = 0; i < 4; ++i) {
+    p->prof_ms[i] = 0.0;
+    p->prof_n[i] = 0;
+  }
+  if (e != hipSuccess) return hip_fail(e, "profiling events");
+  return DDM_OK;
+}
+
+ddm_status ddm_plan_get_profile(ddm_plan_t p, uint32_t kind, double* total_ms, int64_t* launches) {
+  ddm_status st = check_plan(p);
+  if (st != DDM_OK) return st;
+  const int s = kind_slot(kind);
+  if (s < 0) return fail(DDM_ERR_INVALID_ARGUMENT, "kernel_kind must be a single ddm_kernel_kind");
+  hipError_t e = prof_drain(p);
+  if (e != hipSuccess) return hip_fail(e, "profiling events");
+  if (total_ms) *total_ms = p->prof_ms[s];
+  if (launches) *launches = p->prof_n[s];
+  return DDM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,199 @@
+// Register/LDS Stockham FFT building blocks for gfx950 (wave64).
+//
+// A length-L transform is held by T = L/E threads, E complex values each.
+// Thread `tid` holds v[e] = x[tid + e*T].  Each pass of radix R applies E/R
+// radix-R butterflies in registers (butterfly j = tid + b*T reads
+// x[j + k*L/R], k < R), then exchanges through LDS so that the next pass again
+// finds its inputs in the same strided distribution.  The last pass needs no
+// exchange: its outputs land in natural order, v[e] = X[tid + e*T].
+//
+// Pass radices are chosen at compile time among 16, 8, 4, 2 and 3; each must
+// divide E.  Twiddles come from a table tw[j] = exp(-2 pi i j / L_tab) built
+// in FP64 on the host and rounded once to FP32; a transform of length L reads
+// it with stride L_tab / L.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ddm {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// multiply by -i
+__device__ __forceinline__ float2 cmul_mi(float2 a) { return make_float2(a.y, -a.x); }
+
+// Forward DFT codelets (kernel exp(-2 pi i jk / R)) on x[0..R-1] in registers.
+template <int R> struct Dft;
+
+template <> struct Dft<2> {
+  __device__ __forceinline__ static void run(float2* x) {
+    float2 a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  }
+};
+
+template <> struct Dft<3> {
+  __device__ __forceinline__ static void run(float2* x) {
+    const float h = 0.86602540378443864676f;  // sqrt(3)/2
+    float2 s = cadd(x[1], x[2]);
+    float2 d = csub(x[1], x[2]);
+    float2 m = make_float2(x[0].x - 0.5f * s.x, x[0].y - 0.5f * s.y);
+    // -i * h * d
+    float2 r = make_float2(h * d.y, -h * d.x);
+    x[0] = cadd(x[0], s);
+    x[1] = cadd(m, r);
+    x[2] = csub(m, r);
+  }
+};
+
+template <> struct Dft<4> {
+  __device__ __forceinline__ static void run(float2* x) {
+    float2 t0 = cadd(x[0], x[2]), t1 = csub(x[0], x[2]);
+    float2 t2 = cadd(x[1], x[3]), t3 = cmul_mi(csub(x[1], x[3]));
+    x[0] = cadd(t0, t2);
+    x[2] = csub(t0, t2);
+    x[1] = cadd(t1, t3);
+    x[3] = csub(t1, t3);
+  }
+};
+
+template <> struct Dft<8> {
+  __device__ __forceinline__ static void run(float2* x) {
+    const float c = 0.70710678118654752440f;
+    float2 e[4] = {x[0], x[2], x[4], x[6]};
+    float2 o[4] = {x[1], x[3], x[5], x[7]};
+    Dft<4>::run(e);
+    Dft<4>::run(o);
+    // o[k] *= exp(-2 pi i k / 8)
+    o[1] = make_float2(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x));
+    o[2] = cmul_mi(o[2]);
+    o[3] = make_float2(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      x[k] = cadd(e[k], o[k]);
+      x[k + 4] = csub(e[k], o[k]);
+    }
+  }
+};
+
+template <> struct Dft<16> {
+  __device__ __forceinline__ static void run(float2* x) {
+    // exp(-2 pi i k / 16), k = 0..7
+    const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;
+    const float c2 = 0.70710678118654752440f;
+    float2 e[8], o[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      e[k] = x[2 * k];
+      o[k] = x[2 * k + 1];
+    }
+    Dft<8>::run(e);
+    Dft<8>::run(o);
+    const float2 w[8] = {make_float2(1.f, 0.f),  make_float2(c1, -s1),  make_float2(c2, -c2),
+                         make_float2(s1, -c1),   make_float2(0.f, -1.f), make_float2(-s1, -c1),
+                         make_float2(-c2, -c2),  make_float2(-c1, -s1)};
+#pragma unroll
+    for (int k = 1; k < 8; ++k) o[k] = cmul(o[k], w[k]);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      x[k] = cadd(e[k], o[k]);
+      x[k + 8] = csub(e[k], o[k]);
+    }
+  }
+};
+
+// Largest radix for the remaining length `rem` that also divides E.
+constexpr int pick_radix(int rem, int E) {
+  return (rem % 16 == 0 && E % 16 == 0) ? 16
+       : (rem % 8 == 0 && E % 8 == 0)   ? 8
+       : (rem % 4 == 0 && E % 4 == 0)   ? 4
+       : (rem % 2 == 0 && E % 2 == 0)   ? 2
+       : (rem % 3 == 0 && E % 3 == 0)   ? 3
+                                         : 0;
+}
+
+constexpr bool fft_schedule_ok(int L, int E, int ns = 1) {
+  return ns == L ? true : (pick_radix(L / ns, E) == 0 ? false : fft_schedule_ok(L, E, ns * pick_radix(L / ns, E)));
+}
+
+// LDS view of one transform: element i lives at base[i * STR].
+template <int STR> struct LdsView {
+  float2* base;
+  __device__ __forceinline__ float2& operator[](int i) const { return base[i * STR]; }
+};
+
+// Pass of radix R with span NS (product of the radices already applied).
+// Exchanges through LDS unless it is the last pass.  Every thread of the
+// workgroup must call it (it contains __syncthreads()).
+template <int L, int E, int R, int NS, int STR>
+__device__ __forceinline__ void stockham_pass(float2 (&v)[E], LdsView<STR> buf, int tid,
+                                              const float2* __restrict__ tw, int tws) {
+  constexpr int T = L / E;
+  constexpr int NB = E / R;
+  constexpr bool LAST = (NS * R == L);
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = tid + b * T;
+    float2 x[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) x[k] = v[b + k * NB];
+    const int jm = (NS == 1) ? 0 : (j % NS);
+    if (NS > 1) {
+      const int step = jm * (L / (NS * R)) * tws;
+#pragma unroll
+      for (int k = 1; k < R; ++k) x[k] = cmul(x[k], tw[k * step]);
+    }
+    Dft<R>::run(x);
+    if (LAST) {
+#pragma unroll
+      for (int k = 0; k < R; ++k) v[b + k * NB] = x[k];
+    } else {
+      const int base = (j / NS) * NS * R + jm;
+#pragma unroll
+      for (int k = 0; k < R; ++k) buf[base + k * NS] = x[k];
+    }
+  }
+  if (!LAST) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = buf[tid + e * T];
+    __syncthreads();
+  }
+}
+
+template <int L, int E, int NS, int STR>
+struct FftPasses {
+  static constexpr int R = pick_radix(L / NS, E);
+  static_assert(R != 0, "length not reachable with radices dividing E");
+  __device__ __forceinline__ static void run(float2 (&v)[E], LdsView<STR> buf, int tid,
+                                             const float2* __restrict__ tw, int tws) {
+    stockham_pass<L, E, R, NS, STR>(v, buf, tid, tw, tws);
+    if constexpr (NS * R < L) FftPasses<L, E, NS * R, STR>::run(v, buf, tid, tw, tws);
+  }
+};
+
+// Forward transform, exp(-2 pi i n k / L), unnormalised.
+template <int L, int E, int STR>
+__device__ __forceinline__ void fft_forward(float2 (&v)[E], LdsView<STR> buf, int tid,
+                                            const float2* __restrict__ tw, int tws) {
+  static_assert(L % E == 0, "E must divide L");
+  static_assert(fft_schedule_ok(L, E), "no radix schedule");
+  FftPasses<L, E, 1, STR>::run(v, buf, tid, tw, tws);
+}
+
+// Inverse transform, exp(+2 pi i n k / L), unnormalised (conjugation trick).
+template <int L, int E, int STR>
+__device__ __forceinline__ void fft_inverse(float2 (&v)[E], LdsView<STR> buf, int tid,
+                                            const float2* __restrict__ tw, int tws) {
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = cconj(v[e]);
+  fft_forward<L, E, STR>(v, buf, tid, tw, tws);
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = cconj(v[e]);
+}
+
+}  // namespace ddm

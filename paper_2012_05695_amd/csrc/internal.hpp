@@ -1,0 +1,68 @@
+// Host-side internals shared by the C-ABI layer and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ddm.h"
+
+namespace ddm {
+
+// Spectra store between step one and step two: blocks of QB consecutive wave
+// vectors (q order), each block [N][QB] complex, so that one time step of a
+// block is a 128-byte run (FP32) written by the column transform and read by
+// the time transform.
+constexpr int kSpecQB = 16;
+
+// Launch geometry of the time-stage kernel for a given padded length L.
+struct TimeCfg {
+  int L;      // half of the zero-padded length N2 (power of two, >= 16)
+  int E;      // complex values per thread
+  int T;      // threads per wave vector (L / E)
+  int qpw;    // wave vectors per workgroup
+  size_t lds; // dynamic LDS bytes
+};
+TimeCfg time_cfg(int L);
+
+struct RowCfg {
+  int W, E, T, nt;  // transform length, values/thread, threads/transform, transforms/WG
+  size_t lds;
+};
+RowCfg row_cfg(int W, int H);
+
+struct ColCfg {
+  int H, E, T, cw;  // transform length, values/thread, threads/column, columns/WG
+  size_t lds;
+};
+ColCfg col_cfg(int H);
+
+// Device-side description of the kept wave vectors: for each ky row, the
+// first q index of the row and the number of kept kx (kept kx are 0..cnt-1
+// because k2 grows with kx).
+struct QTable {
+  const int32_t* qoff;   // [H] (device)
+  const int32_t* kxcnt;  // [H] (device)
+};
+
+bool supported_spatial(int n);
+
+// ---- launchers (each returns hipSuccess or the launch error) ----
+hipError_t launch_row(hipStream_t s, int pixel, const void* frames, int W, int H, int64_t t0,
+                      int nframes, int precondition, float2* inter, int kxw,
+                      const float2* tw, int tws);
+
+hipError_t launch_col(hipStream_t s, const float2* inter, int H, int kxw, int ntiles,
+                      int64_t t0, int nframes, int N, QTable qt, int64_t q_lo, int64_t q_hi,
+                      int qb, float2* spec, const float2* tw, int tws);
+
+hipError_t launch_time(hipStream_t s, const float2* spec, int qb, int64_t nq_group, int N, int M,
+                       const float2* twN2, float* D_rows);
+
+hipError_t launch_radial(hipStream_t s, const float* D, int64_t nq, int M, int W, int H,
+                         int64_t ca, int64_t cc, QTable qt, const int64_t* thr, int nbins,
+                         double* Dbar, int64_t* counts, int32_t* bin_of_q);
+
+}  // namespace ddm
