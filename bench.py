@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-columns", type=int, default=64,
                     help="kx columns of the oracle sample (all ky, all frames, all lags)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 1 GiB buffer 3 times (HBM byte-counter calibration)")
     ap.add_argument("--kernel-only", default=None,
                     help="run only this many steps and nothing else (for profilers)")
     return ap.parse_args()
@@ -81,6 +83,15 @@ def main():
         sys.exit(2)
     import torch
     from paper_2012_05695_amd import api, synth
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("copied 3 x 1 GiB", file=sys.stderr)
+        return
 
     recipe = {"paper": synth.PAPER, "plain": synth.PLAIN, "large": synth.LARGE}[args.config]
     W, H, N = recipe["W"], recipe["H"], recipe["N"]

@@ -116,7 +116,7 @@ ddm_status ddm_plan_workspace_size(ddm_plan_t plan, size_t* min_bytes, size_t* f
 ddm_status ddm_plan_set_workspace(ddm_plan_t plan, void* workspace_dev, size_t bytes);
 
 /* The full path: frames_dev [N][H][W] (uint8 or uint16 per the plan, row-major,
- * device) -> D_dev [n_q][M] float32 (device), D(q, m) of Eq. (1).
+ * device, 16-byte aligned) -> D_dev [n_q][M] float32 (device), D(q, m) of Eq. (1).
  * Requires a workspace.  Returns DDM_WARN_FP16_SATURATED (result written) if
  * the FP16 spectrum store clipped values. */
 ddm_status ddm_structure_function(ddm_plan_t plan, const void* frames_dev, float* D_dev);

@@ -57,6 +57,7 @@ struct ddm_plan_s {
   // device tables (one allocation)
   void* dev_tables;
   float2 *twW, *twH, *twT;
+  double* ramp;  // 1/(N-m), m < N, FP64 (the ramp vector of Appendix B)
   int32_t *qoff_d, *kxcnt_d;
   // radial thresholds (grown on demand)
   int64_t* thr_d;
@@ -234,7 +235,10 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
   fill_twiddles(tw, W, H);
   fill_twiddles(tw, W + H, 2 * p->L);
   const size_t tw_bytes = align256(ntw * sizeof(float2));
-  const size_t tab_bytes = tw_bytes + 2 * align256(H * sizeof(int32_t));
+  const size_t ramp_bytes = align256((size_t)N * sizeof(double));
+  std::vector<double> ramp(N);
+  for (int m = 0; m < N; ++m) ramp[m] = 1.0 / (double)(N - m);
+  const size_t tab_bytes = tw_bytes + ramp_bytes + 2 * align256(H * sizeof(int32_t));
   hipError_t e = hipMalloc(&p->dev_tables, tab_bytes);
   if (e != hipSuccess) {
     delete p;
@@ -244,9 +248,11 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
   p->twW = (float2*)base;
   p->twH = p->twW + W;
   p->twT = p->twH + H;
-  p->qoff_d = (int32_t*)(base + tw_bytes);
-  p->kxcnt_d = (int32_t*)(base + tw_bytes + align256(H * sizeof(int32_t)));
+  p->ramp = (double*)(base + tw_bytes);
+  p->qoff_d = (int32_t*)(base + tw_bytes + ramp_bytes);
+  p->kxcnt_d = (int32_t*)(base + tw_bytes + ramp_bytes + align256(H * sizeof(int32_t)));
   if ((e = hipMemcpy(p->twW, tw.data(), ntw * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(p->ramp, ramp.data(), N * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(p->qoff_d, p->qoff.data(), H * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(p->kxcnt_d, p->kxcnt.data(), H * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess) {
     hipFree(p->dev_tables);
@@ -382,6 +388,7 @@ ddm_status ddm_structure_function(ddm_plan_t p, const void* frames, float* D) {
   ddm_status st = check_plan(p);
   if (st != DDM_OK) return st;
   if (frames == nullptr || D == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "frames/D is NULL");
+  if (((uintptr_t)frames & 15) != 0) return fail(DDM_ERR_INVALID_ARGUMENT, "frames must be 16-byte aligned");
   if (p->ws == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "no workspace attached (ddm_plan_set_workspace)");
   int fb;
   int64_t gblocks;
@@ -396,7 +403,7 @@ ddm_status ddm_structure_function(ddm_plan_t p, const void* frames, float* D) {
     hipError_t e;
     {
       ProfScope ps(p, DDM_KERNEL_TIME);
-      e = launch_time(p->stream, spec, kSpecQB, q_hi - q_lo, p->N, p->M, p->twT,
+      e = launch_time(p->stream, spec, kSpecQB, q_hi - q_lo, p->N, p->M, p->twT, p->ramp,
                       D + (size_t)q_lo * p->M);
     }
     if (e != hipSuccess) return hip_fail(e, "time transform launch");
@@ -409,6 +416,7 @@ ddm_status ddm_image_spectra(ddm_plan_t p, const void* frames, float* spectra) {
   if (st != DDM_OK) return st;
   if (frames == nullptr || spectra == nullptr)
     return fail(DDM_ERR_INVALID_ARGUMENT, "frames/spectra is NULL");
+  if (((uintptr_t)frames & 15) != 0) return fail(DDM_ERR_INVALID_ARGUMENT, "frames must be 16-byte aligned");
   if (p->ws == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "no workspace attached (ddm_plan_set_workspace)");
   const size_t fib = p->frame_inter_bytes;
   int fb = (int)std::min<size_t>(p->fb_target, std::max<size_t>(1, p->ws_bytes / fib));
@@ -423,7 +431,7 @@ ddm_status ddm_structure_from_spectra(ddm_plan_t p, const float* spectra, float*
   hipError_t e;
   {
     ProfScope ps(p, DDM_KERNEL_TIME);
-    e = launch_time(p->stream, (const float2*)spectra, 1, p->nq, p->N, p->M, p->twT, D);
+    e = launch_time(p->stream, (const float2*)spectra, 1, p->nq, p->N, p->M, p->twT, p->ramp, D);
   }
   if (e != hipSuccess) return hip_fail(e, "time transform launch");
   return DDM_OK;

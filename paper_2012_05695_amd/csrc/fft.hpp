@@ -93,11 +93,14 @@ template <> struct Dft<16> {
     }
     Dft<8>::run(e);
     Dft<8>::run(o);
-    const float2 w[8] = {make_float2(1.f, 0.f),  make_float2(c1, -s1),  make_float2(c2, -c2),
-                         make_float2(s1, -c1),   make_float2(0.f, -1.f), make_float2(-s1, -c1),
-                         make_float2(-c2, -c2),  make_float2(-c1, -s1)};
-#pragma unroll
-    for (int k = 1; k < 8; ++k) o[k] = cmul(o[k], w[k]);
+    // constant twiddles, with the trivial ones (k = 2, 4, 6) written out
+    o[1] = cmul(o[1], make_float2(c1, -s1));
+    o[2] = make_float2(c2 * (o[2].x + o[2].y), c2 * (o[2].y - o[2].x));
+    o[3] = cmul(o[3], make_float2(s1, -c1));
+    o[4] = cmul_mi(o[4]);
+    o[5] = cmul(o[5], make_float2(-s1, -c1));
+    o[6] = make_float2(c2 * (o[6].y - o[6].x), -c2 * (o[6].x + o[6].y));
+    o[7] = cmul(o[7], make_float2(-c1, -s1));
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       x[k] = cadd(e[k], o[k]);
@@ -120,17 +123,36 @@ constexpr bool fft_schedule_ok(int L, int E, int ns = 1) {
   return ns == L ? true : (pick_radix(L / ns, E) == 0 ? false : fft_schedule_ok(L, E, ns * pick_radix(L / ns, E)));
 }
 
-// LDS view of one transform: element i lives at base[i * STR].
-template <int STR> struct LdsView {
+// LDS view of one transform: element i lives at base[(i + pad(i)) * STR],
+// pad(i) = i / 16 when PAD (one spare slot per 16 elements, which spreads the
+// stride-16 writes of a radix-16 pass over the LDS banks).
+template <int STR, bool PAD = false> struct LdsView {
   float2* base;
-  __device__ __forceinline__ float2& operator[](int i) const { return base[i * STR]; }
+  __device__ __forceinline__ static int slot(int i) { return PAD ? i + (i >> 4) : i; }
+  __device__ __forceinline__ float2& operator[](int i) const { return base[slot(i) * STR]; }
 };
+
+// Padded length of an L-element transform buffer.
+template <bool PAD> constexpr int lds_len(int L) { return PAD ? L + L / 16 : L; }
+
+// Synchronisation of the threads that share one transform: a whole workgroup,
+// or only the wavefront when the transform lives inside one wave (LDS
+// operations of one wave execute in order, so a compiler fence suffices).
+template <bool WAVE> __device__ __forceinline__ void group_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
 
 // Pass of radix R with span NS (product of the radices already applied).
 // Exchanges through LDS unless it is the last pass.  Every thread of the
 // workgroup must call it (it contains __syncthreads()).
-template <int L, int E, int R, int NS, int STR>
-__device__ __forceinline__ void stockham_pass(float2 (&v)[E], LdsView<STR> buf, int tid,
+template <int L, int E, int R, int NS, int STR, bool PAD, bool WAVE>
+__device__ __forceinline__ void stockham_pass(float2 (&v)[E], LdsView<STR, PAD> buf, int tid,
                                               const float2* __restrict__ tw, int tws) {
   constexpr int T = L / E;
   constexpr int NB = E / R;
@@ -158,40 +180,40 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[E], LdsView<STR> buf, 
     }
   }
   if (!LAST) {
-    __syncthreads();
+    group_sync<WAVE>();
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = buf[tid + e * T];
-    __syncthreads();
+    group_sync<WAVE>();
   }
 }
 
-template <int L, int E, int NS, int STR>
+template <int L, int E, int NS, int STR, bool PAD, bool WAVE>
 struct FftPasses {
   static constexpr int R = pick_radix(L / NS, E);
   static_assert(R != 0, "length not reachable with radices dividing E");
-  __device__ __forceinline__ static void run(float2 (&v)[E], LdsView<STR> buf, int tid,
+  __device__ __forceinline__ static void run(float2 (&v)[E], LdsView<STR, PAD> buf, int tid,
                                              const float2* __restrict__ tw, int tws) {
-    stockham_pass<L, E, R, NS, STR>(v, buf, tid, tw, tws);
-    if constexpr (NS * R < L) FftPasses<L, E, NS * R, STR>::run(v, buf, tid, tw, tws);
+    stockham_pass<L, E, R, NS, STR, PAD, WAVE>(v, buf, tid, tw, tws);
+    if constexpr (NS * R < L) FftPasses<L, E, NS * R, STR, PAD, WAVE>::run(v, buf, tid, tw, tws);
   }
 };
 
 // Forward transform, exp(-2 pi i n k / L), unnormalised.
-template <int L, int E, int STR>
-__device__ __forceinline__ void fft_forward(float2 (&v)[E], LdsView<STR> buf, int tid,
+template <int L, int E, int STR, bool PAD = false, bool WAVE = false>
+__device__ __forceinline__ void fft_forward(float2 (&v)[E], LdsView<STR, PAD> buf, int tid,
                                             const float2* __restrict__ tw, int tws) {
   static_assert(L % E == 0, "E must divide L");
   static_assert(fft_schedule_ok(L, E), "no radix schedule");
-  FftPasses<L, E, 1, STR>::run(v, buf, tid, tw, tws);
+  FftPasses<L, E, 1, STR, PAD, WAVE>::run(v, buf, tid, tw, tws);
 }
 
 // Inverse transform, exp(+2 pi i n k / L), unnormalised (conjugation trick).
-template <int L, int E, int STR>
-__device__ __forceinline__ void fft_inverse(float2 (&v)[E], LdsView<STR> buf, int tid,
+template <int L, int E, int STR, bool PAD = false, bool WAVE = false>
+__device__ __forceinline__ void fft_inverse(float2 (&v)[E], LdsView<STR, PAD> buf, int tid,
                                             const float2* __restrict__ tw, int tws) {
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = cconj(v[e]);
-  fft_forward<L, E, STR>(v, buf, tid, tw, tws);
+  fft_forward<L, E, STR, PAD, WAVE>(v, buf, tid, tw, tws);
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = cconj(v[e]);
 }

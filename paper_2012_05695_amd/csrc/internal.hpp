@@ -59,7 +59,7 @@ hipError_t launch_col(hipStream_t s, const float2* inter, int H, int kxw, int nt
                       int qb, float2* spec, const float2* tw, int tws);
 
 hipError_t launch_time(hipStream_t s, const float2* spec, int qb, int64_t nq_group, int N, int M,
-                       const float2* twN2, float* D_rows);
+                       const float2* twN2, const double* ramp, float* D_rows);
 
 hipError_t launch_radial(hipStream_t s, const float* D, int64_t nq, int M, int W, int H,
                          int64_t ca, int64_t cc, QTable qt, const int64_t* thr, int nbins,

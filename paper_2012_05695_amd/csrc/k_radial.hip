@@ -36,25 +36,67 @@ __global__ void __launch_bounds__(256) k_radial(const float* __restrict__ D, int
   const int b = blockIdx.x;
   const int m = blockIdx.y * blockDim.x + threadIdx.x;
   const int64_t lo_t = thr[b], hi_t = thr[b + 1];
+  // the bin's kx interval of every ky row, computed once per workgroup in
+  // chunks of blockDim rows and compacted (in ky order) into LDS
+  __shared__ int2 rows[256];
+  __shared__ int nrows_s;
   double acc = 0.0;
   int64_t wsum = 0;
-  for (int ky = 0; ky < H; ++ky) {
-    const int64_t kys = (ky <= H / 2) ? ky : ky - H;
-    const int64_t base = kys * kys * cc;
-    const int64_t cnt = kxcnt[ky];
-    if (cnt == 0 || base >= hi_t) continue;
-    const int64_t lo = first_kx(lo_t - base, ca, cnt);
-    const int64_t hi = first_kx(hi_t - base, ca, cnt);
-    if (lo >= hi) continue;
-    const int64_t q0 = qoff[ky];
-    for (int64_t kx = lo; kx < hi; ++kx) {
-      const int w = (kx > 0 && kx < W / 2) ? 2 : 1;
-      wsum += w;
-      if (m < M) acc += (double)w * (double)D[(size_t)(q0 + kx) * M + m];
+  for (int ky0 = 0; ky0 < H; ky0 += blockDim.x) {
+    if (threadIdx.x == 0) nrows_s = 0;
+    __syncthreads();
+    const int ky = ky0 + (int)threadIdx.x;
+    int2 iv = make_int2(0, 0);
+    if (ky < H) {
+      const int64_t kys = (ky <= H / 2) ? ky : ky - H;
+      const int64_t base = kys * kys * cc;
+      const int64_t cnt = kxcnt[ky];
+      if (cnt > 0 && base < hi_t) {
+        iv.x = (int)first_kx(lo_t - base, ca, cnt);
+        iv.y = (int)first_kx(hi_t - base, ca, cnt);
+      }
+    }
+    // compaction that keeps ky order: prefix count over the workgroup
+    const bool has = iv.x < iv.y;
+    const unsigned long long ball = __ballot(has);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ int wcount[4];
+    if (lane == 0) wcount[wave] = __popcll(ball);
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wave; ++w) before += wcount[w];
+    before += __popcll(ball & ((1ull << lane) - 1ull));
+    if (has) rows[before] = make_int2(ky, (iv.y - iv.x) << 16 | iv.x);
+    if (threadIdx.x == blockDim.x - 1) nrows_s = before + (has ? 1 : 0);
+    __syncthreads();
+    const int nr = nrows_s;
+    for (int r = 0; r < nr; ++r) {
+    const int2 rr = rows[r];
+    const int ky_r = rr.x;
+    const int64_t lo = rr.y & 0xFFFF, hi = lo + (rr.y >> 16);
+    const int64_t q0 = qoff[ky_r];
+    for (int64_t kx = lo; kx < hi; ++kx) wsum += (kx > 0 && kx < W / 2) ? 2 : 1;
+    if (m < M) {
+      // eight rows in flight per step; the sum itself stays in q order
+      const float* col = D + (size_t)q0 * M + m;
+      int64_t kx = lo;
+      for (; kx + 8 <= hi; kx += 8) {
+        float d[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) d[u] = col[(size_t)(kx + u) * M];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int64_t k = kx + u;
+          acc += ((k > 0 && k < W / 2) ? 2.0 : 1.0) * (double)d[u];
+        }
+      }
+      for (; kx < hi; ++kx) acc += ((kx > 0 && kx < W / 2) ? 2.0 : 1.0) * (double)col[(size_t)kx * M];
     }
     if (bin_of_q != nullptr && blockIdx.y == 0) {
       for (int64_t kx = lo + threadIdx.x; kx < hi; kx += blockDim.x) bin_of_q[q0 + kx] = b;
     }
+    }
+    __syncthreads();  // rows[] is rewritten by the next chunk
   }
   if (m < M) Dbar[(size_t)b * M + m] = (wsum > 0) ? acc / (double)wsum : 0.0;
   if (blockIdx.y == 0 && threadIdx.x == 0) counts[b] = wsum;

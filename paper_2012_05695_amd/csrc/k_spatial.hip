@@ -16,39 +16,72 @@
 
 namespace ddm {
 
+// Unpack the pixels of one 16-byte load.
+template <typename PIX> struct Pix16;
+template <> struct Pix16<uint16_t> {
+  static constexpr int n = 8;
+  __device__ __forceinline__ static int get(const uint4& a, int k) {
+    const uint32_t w = (k < 2) ? a.x : (k < 4) ? a.y : (k < 6) ? a.z : a.w;
+    return (int)((w >> (16 * (k & 1))) & 0xFFFFu);
+  }
+};
+template <> struct Pix16<uint8_t> {
+  static constexpr int n = 16;
+  __device__ __forceinline__ static int get(const uint4& a, int k) {
+    const uint32_t w = (k < 4) ? a.x : (k < 8) ? a.y : (k < 12) ? a.z : a.w;
+    return (int)((w >> (8 * (k & 3))) & 0xFFu);
+  }
+};
+
 template <int W, int E, typename PIX>
-__global__ void __launch_bounds__(1024) k_row(const PIX* __restrict__ frames, int H, int64_t t0,
-                                              int precondition, float2* __restrict__ inter, int kxw,
-                                              const float2* __restrict__ tw, int tws) {
+__global__ void __launch_bounds__(256) k_row(const PIX* __restrict__ frames, int H, int64_t t0,
+                                             int precondition, float2* __restrict__ inter, int kxw,
+                                             const float2* __restrict__ tw, int tws) {
   constexpr int T = W / E;
+  constexpr bool WAVE = (T <= 64) && (64 % T == 0);  // a transform inside one wavefront
+  constexpr int WL = lds_len<true>(W);
   extern __shared__ float2 lds_row[];
   const int p = threadIdx.x / T;          // transform (row pair) within the workgroup
   const int tid = threadIdx.x % T;
   const int nt = blockDim.x / T;
-  const int y0 = (blockIdx.x * nt + p) * 2;
+  const int ybase = blockIdx.x * nt * 2;
+  const int y0 = ybase + 2 * p;
   const int64_t t = t0 + blockIdx.y;
-  const size_t plane = (size_t)H * W;
-  const PIX* r0 = frames + (size_t)t * plane + (size_t)y0 * W;
-  const PIX* r1 = r0 + W;
-  const PIX* b0 = frames + (size_t)y0 * W;  // frame 0, same rows
-  const PIX* b1 = b0 + W;
 
+  // Stage rows [ybase, ybase + 2 nt) of frame t (minus frame 0) with 16-byte
+  // loads: row 2p' + c of the block becomes component c of transform p'.
+  {
+    constexpr int V = Pix16<PIX>::n;
+    const uint4* src = reinterpret_cast<const uint4*>(frames + ((size_t)t * H + ybase) * W);
+    const uint4* ref = reinterpret_cast<const uint4*>(frames + (size_t)ybase * W);
+    const int nvec = 2 * nt * W / V;
+    float* f = reinterpret_cast<float*>(lds_row);
+#pragma unroll 4
+    for (int g = threadIdx.x; g < nvec; g += blockDim.x) {
+      const uint4 a = src[g];
+      uint4 b = make_uint4(0u, 0u, 0u, 0u);
+      if (precondition) b = ref[g];
+      const int pix = g * V;
+      const int r = pix / W, n0 = pix % W;
+      float* dst = f + 2 * ((r >> 1) * WL) + (r & 1);
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        const int n = n0 + k;
+        dst[2 * LdsView<1, true>::slot(n)] = (float)(Pix16<PIX>::get(a, k) - Pix16<PIX>::get(b, k));
+      }
+    }
+  }
+  __syncthreads();
+
+  LdsView<1, true> buf{lds_row + p * WL};
   float2 v[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int n = tid + e * T;
-    int a = (int)r0[n], b = (int)r1[n];
-    if (precondition) {
-      a -= (int)b0[n];
-      b -= (int)b1[n];
-    }
-    v[e] = make_float2((float)a, (float)b);
-  }
-  LdsView<1> buf{lds_row + p * W};
-  fft_forward<W, E, 1>(v, buf, tid, tw, tws);
+  for (int e = 0; e < E; ++e) v[e] = buf[tid + e * T];
+  group_sync<WAVE>();
+  fft_forward<W, E, 1, true, WAVE>(v, buf, tid, tw, tws);
 #pragma unroll
   for (int e = 0; e < E; ++e) buf[tid + e * T] = v[e];
-  __syncthreads();
+  group_sync<WAVE>();
   float2* o0 = inter + ((size_t)blockIdx.y * H + y0) * kxw;
   float2* o1 = o0 + kxw;
 #pragma unroll
@@ -115,7 +148,7 @@ RowCfg row_cfg(int W, int H) {
   if (nt < 1) nt = 1;
   while (nt > 1 && ((H / 2) % nt) != 0) nt >>= 1;
   c.nt = nt;
-  c.lds = (size_t)nt * W * sizeof(float2);
+  c.lds = (size_t)nt * (W + W / 16) * sizeof(float2);
   return c;
 }
 

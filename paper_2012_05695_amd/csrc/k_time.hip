@@ -7,173 +7,283 @@
 // with prefix sums S(k) = sum_{j<k} |x_j|^2 (the closed form of the recursion
 // Eq. (B3)) and the acyclic autocorrelation c(m) = sum_n conj(x_n) x_{n+m},
 // obtained by zero padding to N2 = 2L (Eq. (B4), L = 2^ceil(log2 N)), a
-// forward FFT, squared modulus, inverse FFT (Appendix B, the five steps).
+// forward FFT, squared modulus, inverse FFT, and the ramp 1/(N-m)
+// (Appendix B, the five steps).
 //
 // MI355X formulation of the same computation:
-//  * the per-q FP64 temporal mean is subtracted first (D depends only on
-//    differences of x, so any per-q constant offset cancels exactly; removing
-//    it keeps the FP32 transforms away from cancellation);
+//  * a per-q constant close to the temporal mean is subtracted first.  D
+//    depends only on differences of x, so any constant offset per q cancels
+//    exactly; removing it keeps the FP32 transforms and the squared moduli
+//    away from cancellation.  The constant is the FP32 mean (its own rounding
+//    error is irrelevant: it is the same constant for every sample);
 //  * the N2-point forward FFT of the half-zero sequence is done as two L-point
 //    FFTs: X_{2j} = FFT_L(x)_j and X_{2j+1} = FFT_L(x_n w^n)_j, w = e^{-2 pi i/N2};
 //  * the real power spectrum P is inverted with one complex L-point IFFT of
 //    P_even + i P_odd, separated afterwards by conjugate symmetry:
 //    with z = IFFT(P_e + i P_o), a_m = (z_m + conj z_{L-m})/2 and
 //    b_m = (z_m - conj z_{L-m})/(2i), sum_k P_k e^{2 pi i k m/N2} = a_m + e^{2 pi i m/N2} b_m;
-//  * S and the final combination are FP64; D is rounded to FP32 once.
+//  * the prefix sums S are accumulated in FP64 and the final combination
+//    S(N-m) + S(N) - S(m) - 2 Re c(m) and the ramp are FP64 (the cancellation
+//    at small lags needs it); D is rounded to FP32 once.
+//
+// Work layout: a workgroup holds QPW wave vectors; each is transformed by
+// T = L/E threads with E values each (E = 16 by default).  For L <= 1024 a wave vector lives
+// inside one wavefront, so after the cooperative load every wave runs on its
+// own (wave-local sync, shuffle reductions); longer transforms span waves and
+// synchronise the workgroup.  LDS per wave vector: the offset-free sequence
+// (later its prefix sums, as doubles) and one exchange buffer; per workgroup
+// the L-point twiddle table, read by every pass of all three transforms.  Global reads
+// use buffer loads (scalar base, 32-bit offsets; reads past the described
+// range return 0, which supplies the zero padding).
+#include <cstdlib>
+
 #include "fft.hpp"
 #include "internal.hpp"
 
 namespace ddm {
 
-template <int L, int E>
-__global__ void __launch_bounds__(512) k_time(const float2* __restrict__ spec, int qb, int qpw,
-                                               int64_t nq, int N, int M,
-                                               const float2* __restrict__ twN2,
-                                               float* __restrict__ D) {
+namespace {
+
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer descriptor, gfx9 family
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kRsrcWord3);
+}
+__device__ __forceinline__ float2 ld_f2(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+}
+__device__ __forceinline__ double ld_f64(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+}
+
+// Sum over the T consecutive threads of a group (tid = index in the group).
+// T <= 64: xor butterfly inside the wave (every lane ends with the same bits).
+// T > 64: per-wave butterfly, then the T/64 wave totals through LDS.
+template <int T, typename V>
+__device__ __forceinline__ V group_sum(V v, int tid, V* scratch) {
+  constexpr int WT = T < 64 ? T : 64;
+#pragma unroll
+  for (int o = WT / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WT);
+  if constexpr (T > 64) {
+    if ((tid & 63) == 0) scratch[tid >> 6] = v;
+    __syncthreads();
+    V s = 0;
+#pragma unroll
+    for (int i = 0; i < T / 64; ++i) s += scratch[i];
+    __syncthreads();
+    v = s;
+  }
+  return v;
+}
+
+// Exclusive prefix sum over the group; *total receives the group sum.
+template <int T>
+__device__ __forceinline__ double group_excl_scan(double v, int tid, double* scratch, double* total) {
+  constexpr int WT = T < 64 ? T : 64;
+  const int l = tid % WT;
+  double incl = v;
+#pragma unroll
+  for (int o = 1; o < WT; o <<= 1) {
+    const double y = __shfl_up(incl, o, WT);
+    if (l >= o) incl += y;
+  }
+  double excl = __shfl_up(incl, 1, WT);
+  if (l == 0) excl = 0.0;
+  double wtot = __shfl(incl, WT - 1, WT);
+  if constexpr (T > 64) {
+    if (l == WT - 1) scratch[tid >> 6] = wtot;
+    __syncthreads();
+    double before = 0.0, all = 0.0;
+#pragma unroll
+    for (int i = 0; i < T / 64; ++i) {
+      const double s = scratch[i];
+      if (i < (tid >> 6)) before += s;
+      all += s;
+    }
+    __syncthreads();
+    excl += before;
+    wtot = all;
+  }
+  *total = wtot;
+  return excl;
+}
+
+}  // namespace
+
+// QB: layout of the input time series.  QB == 1: plain q-major [q][N].
+// QB > 1: the blocked store [q / QB][N][QB] written by the column transform.
+template <int L, int QPW, int QB, int E, bool TWL>
+__global__ void __launch_bounds__(QPW * (L / E)) k_time(const float2* __restrict__ spec, int64_t nq,
+                                                       int N, int M, const float2* __restrict__ twN2,
+                                                       const double* __restrict__ ramp,
+                                                       float* __restrict__ D) {
   constexpr int T = L / E;
-  constexpr int XS = L + 1;  // per-q stride of the complex buffer (breaks bank aliasing)
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  float2* xbuf = reinterpret_cast<float2*>(lds_raw);
-  double* sbuf = reinterpret_cast<double*>(lds_raw + sizeof(float2) * (size_t)XS * qpw);
+  constexpr bool WAVE = (T <= 64);
+  constexpr int XS = lds_len<true>(L) + 1;  // staging stride (odd: spreads the transposed writes)
+  constexpr int YS = lds_len<true>(L);      // exchange buffer stride
+  constexpr int NT = QPW * T;
+  __shared__ float2 xall[QPW * XS];
+  __shared__ float2 yall[QPW * YS];
+  __shared__ double red[QPW * (T > 64 ? T / 64 : 1)];
+  __shared__ float redf[QPW * (T > 64 ? T / 64 : 1)];
+  // L-point FFT twiddles exp(-2 pi i j / L), shared by the workgroup's
+  // transforms (TWL), else read from the global table at stride 2
+  __shared__ float2 twl[TWL ? L : 1];
 
   // Workgroup -> first wave vector.  When a workgroup covers only part of a
-  // layout block (qpw < qb), the qb/qpw workgroups that share the block's
+  // layout block (QPW < QB), the QB/QPW workgroups that share the block's
   // cache lines get ids that the round-robin dispatcher sends to the same XCD.
   const int64_t id = blockIdx.x;
   int64_t q0;
-  if (qpw >= qb) {
-    q0 = id * qpw;
+  if constexpr (QPW >= QB) {
+    q0 = id * QPW;
   } else {
-    const int nsub = qb / qpw;
-    const int64_t G = 8LL * nsub;
-    const int64_t r = id % G;
-    q0 = ((id / G) * 8 + (r % 8)) * qb + (r / 8) * qpw;
+    constexpr int nsub = QB / QPW;
+    const int64_t r = id % (8 * nsub);
+    q0 = ((id / (8 * nsub)) * 8 + (r % 8)) * QB + (r / 8) * QPW;
   }
   if (q0 >= nq) return;  // uniform for the whole workgroup
+
+  const __amdgpu_buffer_rsrc_t tw_r = make_rsrc(twN2, 2u * L * sizeof(float2));
+  const __amdgpu_buffer_rsrc_t ramp_r = make_rsrc(ramp, (uint32_t)N * sizeof(double));
+  if constexpr (TWL) {
+    for (int j = threadIdx.x; j < L; j += NT) twl[j] = ld_f2(tw_r, (uint32_t)(2 * j) * 8u);
+  }
+  const float2* ftw = TWL ? twl : twN2;
+  constexpr int ftws = TWL ? 1 : 2;
+
+  // ---- cooperative load of QPW time sequences into LDS, [q][t] ----
+  {
+    __amdgpu_buffer_rsrc_t in_r;
+    if constexpr (QB == 1) {
+      const int64_t nvalid = (nq - q0) < QPW ? (nq - q0) : QPW;
+      in_r = make_rsrc(spec + (size_t)q0 * N, (uint32_t)(nvalid * N * sizeof(float2)));
+    } else {
+      // rows t < N of this sub-block; t >= N falls past the range and reads 0
+      const int64_t blk = q0 / QB;
+      const int sub = (int)(q0 % QB);
+      in_r = make_rsrc(spec + (size_t)blk * N * QB + sub,
+                       (uint32_t)(((size_t)(N - 1) * QB + QPW) * sizeof(float2)));
+    }
+    float2 ld[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int f = threadIdx.x + r * NT;
+      uint32_t off;
+      if constexpr (QB == 1) {
+        const int i = f / L, t = f % L;
+        off = (t < N) ? (uint32_t)(i * N + t) * 8u : 0xFFFFFFF0u;
+      } else {
+        const int t = f / QPW, i = f % QPW;
+        off = (uint32_t)(t * QB + i) * 8u;
+      }
+      ld[r] = ld_f2(in_r, off);
+    }
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int f = threadIdx.x + r * NT;
+      int t, i;
+      if constexpr (QB == 1) { i = f / L; t = f % L; }
+      else { t = f / QPW; i = f % QPW; }
+      xall[i * XS + LdsView<1, true>::slot(t)] = ld[r];
+    }
+  }
+  __syncthreads();
 
   const int qi = threadIdx.x / T;
   const int tid = threadIdx.x % T;
   const int64_t q = q0 + qi;
-  const bool qvalid = q < nq;
+  LdsView<1, true> xb{xall + qi * XS};
+  LdsView<1, true> yb{yall + qi * YS};
+  double* xd = reinterpret_cast<double*>(xall + qi * XS);  // the same bytes, as doubles
+  double* scratch = red + qi * (T > 64 ? T / 64 : 1);
+  float* scratchf = redf + qi * (T > 64 ? T / 64 : 1);
 
-  // ---- cooperative load of qpw time sequences into LDS, [q][t] ----
-  // element (q, t) of the store sits at ((q / qb) * N + t) * qb + q % qb:
-  // qb = 1 is plain q-major input, qb > 1 the blocked store.
+  // ---- offset: FP32 mean over the contiguous chunk [tid*E, tid*E+E), fixed order ----
   {
-    const int total = N * qpw;
-    const int nthr = blockDim.x;
-    for (int f = threadIdx.x; f < total; f += nthr) {
-      int t, i;
-      if (qb == 1) { i = f / N; t = f - i * N; }
-      else { t = f / qpw; i = f - t * qpw; }
-      const int64_t qq = q0 + i;
-      float2 val = make_float2(0.f, 0.f);
-      if (qq < nq) val = spec[((size_t)(qq / qb) * N + t) * qb + (qq % qb)];
-      xbuf[i * XS + t] = val;
+    float2 c[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) c[i] = xb[tid * E + i];
+    float sr[E / 2], si[E / 2];
+#pragma unroll
+    for (int i = 0; i < E / 2; ++i) {
+      sr[i] = c[2 * i].x + c[2 * i + 1].x;
+      si[i] = c[2 * i].y + c[2 * i + 1].y;
     }
-    for (int f = threadIdx.x; f < (L - N) * qpw; f += nthr) {
-      const int i = f / (L - N), t = N + (f - i * (L - N));
-      xbuf[i * XS + t] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int w = E / 4; w > 0; w >>= 1)
+#pragma unroll
+      for (int i = 0; i < w; ++i) {
+        sr[i] += sr[i + w];
+        si[i] += si[i + w];
+      }
+    const float inv_n = 1.0f / (float)N;
+    const float mr = group_sum<T>(sr[0], tid, scratchf) * inv_n;
+    const float mi = group_sum<T>(si[0], tid, scratchf) * inv_n;
+    // offset-free sequence x' (FP32), zero beyond N, written back in place
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int n = tid * E + i;
+      xb[n] = (n < N) ? make_float2(c[i].x - mr, c[i].y - mi) : make_float2(0.f, 0.f);
     }
   }
-  __syncthreads();
-
-  float2* xb = xbuf + qi * XS;
-  double* sb = sbuf + (size_t)qi * L;
-  float2 v[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = xb[tid + e * T];
-
-  // ---- FP64 temporal mean, reduced in a fixed order ----
-  double sr = 0.0, si = 0.0;
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    sr += (double)v[e].x;
-    si += (double)v[e].y;
-  }
-  sb[tid] = sr;
-  sb[T + tid] = si;
-  __syncthreads();
-  double mr = 0.0, mi = 0.0;
-  for (int k = 0; k < T; ++k) {
-    mr += sb[k];
-    mi += sb[T + k];
-  }
-  mr /= (double)N;
-  mi /= (double)N;
-  __syncthreads();
-
-  // ---- offset-free sequence x' (FP32) and |x'|^2 (exact in FP64) ----
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int n = tid + e * T;
-    if (n < N) {
-      v[e] = make_float2((float)((double)v[e].x - mr), (float)((double)v[e].y - mi));
-    } else {
-      v[e] = make_float2(0.f, 0.f);
-    }
-    sb[n] = (double)v[e].x * (double)v[e].x + (double)v[e].y * (double)v[e].y;
-  }
-  __syncthreads();
-
-  // ---- prefix sums S(k) = sum_{j<k} |x'_j|^2, FP64, fixed order ----
-  // each thread owns the contiguous chunk [tid*E, tid*E + E)
-  double chunk[E];
-  double ctot = 0.0;
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    chunk[i] = ctot;  // exclusive within the chunk
-    ctot += sb[tid * E + i];
-  }
-  double* tots = reinterpret_cast<double*>(xb);  // xb is free: data lives in v[]
-  tots[tid] = ctot;
-  __syncthreads();
-  double before = 0.0, total = 0.0;
-  for (int k = 0; k < T; ++k) {
-    const double tk = tots[k];
-    if (k < tid) before += tk;
-    total += tk;
-  }
-#pragma unroll
-  for (int i = 0; i < E; ++i) sb[tid * E + i] = before + chunk[i];
-  __syncthreads();  // sb holds S(k), k < L; tots no longer needed
+  group_sync<WAVE>();
 
   // ---- X_odd = FFT_L(x' w^n), w = e^{-2 pi i / N2}; X_even = FFT_L(x') ----
-  LdsView<1> buf{xb};
-  float2 u[E];
+  float2 v[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) u[e] = cmul(v[e], twN2[tid + e * T]);
-  fft_forward<L, E, 1>(u, buf, tid, twN2, 2);
+  for (int e = 0; e < E; ++e) v[e] = cmul(xb[tid + e * T], ld_f2(tw_r, (uint32_t)(tid + e * T) * 8u));
+  fft_forward<L, E, 1, true, WAVE>(v, yb, tid, ftw, ftws);
   float po[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) po[e] = u[e].x * u[e].x + u[e].y * u[e].y;
-  fft_forward<L, E, 1>(v, buf, tid, twN2, 2);
+  for (int e = 0; e < E; ++e) po[e] = v[e].x * v[e].x + v[e].y * v[e].y;
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = xb[tid + e * T];
+  fft_forward<L, E, 1, true, WAVE>(v, yb, tid, ftw, ftws);
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = make_float2(v[e].x * v[e].x + v[e].y * v[e].y, po[e]);
 
-  // ---- z = IFFT_L(P_even + i P_odd), unnormalised ----
-  fft_inverse<L, E, 1>(v, buf, tid, twN2, 2);
+  // ---- z = IFFT_L(P_even + i P_odd), unnormalised; v[e] = z[tid + e*T] ----
+  fft_inverse<L, E, 1, true, WAVE>(v, yb, tid, ftw, ftws);
 #pragma unroll
-  for (int e = 0; e < E; ++e) buf[tid + e * T] = v[e];
-  __syncthreads();
+  for (int e = 0; e < E; ++e) yb[tid + e * T] = v[e];
 
-  // ---- combination: D(m) = (S(N-m) + S(N) - S(m) - 2 Re c(m)) / (N-m) ----
-  if (qvalid) {
-    const double inv_n2 = 1.0 / (2.0 * (double)L);
+  // ---- prefix sums S(k) = sum_{j<k} |x'_j|^2, accumulated in FP64 ----
+  {
+    double s[E];
+    double run = 0.0;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const float2 a = xb[tid * E + i];
+      s[i] = run;
+      run += (double)(a.x * a.x + a.y * a.y);
+    }
+    double total;
+    const double before = group_excl_scan<T>(run, tid, scratch, &total);
+#pragma unroll
+    for (int i = 0; i < E; ++i) xd[LdsView<1, true>::slot(tid * E + i)] = before + s[i];
+    // S(N) sits in slot L (one past the sequence) so that every lag reads the same way
+    if (tid == 0) xd[LdsView<1, true>::slot(L)] = total;
+  }
+  group_sync<WAVE>();
+
+  // ---- D(m) = (S(N-m) + S(N) - S(m) - 2 Re c(m)) / (N-m) ----
+  if (q < nq) {
+    const double sN = xd[LdsView<1, true>::slot(N)];
+    const float inv_l = 1.0f / (float)L;  // 2 / N2, exact
     float* drow = D + (size_t)q * M;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int m = tid + e * T;
       if (m < M) {
-        const float2 zm = buf[m];
-        const float2 zr = buf[(L - m) & (L - 1)];
-        const float2 w = twN2[m];  // (cos th, -sin th), th = 2 pi m / N2
-        const double p = zm.x, qq = zm.y, uu = zr.x, vv = zr.y;
-        const double re_R = 0.5 * ((p + uu) + (double)w.x * (qq + vv) - (double)w.y * (p - uu));
-        const double cm = re_R * inv_n2;
-        const double s_nm = (N - m < L) ? sb[N - m] : total;
-        const double s_m = sb[m];
-        const double dm = ((s_nm + total - s_m) - 2.0 * cm) / (double)(N - m);
+        const float2 zm = v[e];
+        const float2 zr = yb[(L - m) & (L - 1)];
+        const float2 w = ld_f2(tw_r, (uint32_t)m * 8u);  // (cos th, -sin th), th = 2 pi m / N2
+        // 2 Re c(m) = (2/N2) Re sum_k P_k e^{2 pi i k m / N2}
+        const float two_c = 0.5f * ((zm.x + zr.x) + w.x * (zm.y + zr.y) - w.y * (zm.x - zr.x)) * inv_l;
+        const double num = (xd[LdsView<1, true>::slot(N - m)] + sN) - xd[LdsView<1, true>::slot(m)] -
+                           (double)two_c;
+        const double dm = num * ld_f64(ramp_r, (uint32_t)m * 8u);
         // lag 0 pairs every frame with itself: D(q, 0) = 0 exactly by definition
         drow[m] = (m == 0) ? 0.0f : (float)dm;
       }
@@ -181,54 +291,129 @@ __global__ void __launch_bounds__(512) k_time(const float2* __restrict__ spec, i
   }
 }
 
+// Launch shape of the time kernel for a transform length: values per thread
+// E and wave vectors per workgroup QPW (DDM_TIME_E / DDM_TIME_QPW override,
+// for tuning).
+static int env_int(const char* name) {
+  const char* s = std::getenv(name);
+  return s ? std::atoi(s) : 0;
+}
+
+static int time_e(int L) {
+  static const int env = env_int("DDM_TIME_E");
+  if ((env == 8 || env == 16) && L / env >= 1 && L % env == 0 && L >= 16) return env;
+  return 16;
+}
+
+static int time_qpw(int L, int E) {
+  static const int env = env_int("DDM_TIME_QPW");
+  int qpw;
+  if (L <= 256) qpw = 16;
+  else if (L == 512) qpw = 8;
+  else if (L == 1024) qpw = 4;
+  else if (L == 2048) qpw = 2;
+  else qpw = 1;
+  if (env == 1 || env == 2 || env == 4 || env == 8 || env == 16) qpw = env;
+  while (qpw > 1 && (qpw * (L / E) > 1024 || (size_t)qpw * (2 * L + L / 8 + 1) * sizeof(float2) > 160 * 1024))
+    qpw >>= 1;
+  return qpw;
+}
+
 TimeCfg time_cfg(int L) {
   TimeCfg c;
   c.L = L;
-  c.E = 16;
+  c.E = time_e(L);
   c.T = L / c.E;
-  const size_t per_q = sizeof(float2) * (size_t)(L + 1) + sizeof(double) * (size_t)L;
-  int qpw = 16;
-  while (qpw > 1 && per_q * qpw > 163840) qpw >>= 1;
-  while (qpw > 1 && qpw * c.T > 512) qpw >>= 1;
-  c.qpw = qpw;
-  c.lds = per_q * qpw;
+  c.qpw = time_qpw(L, c.E);
+  c.lds = (size_t)c.qpw * (2 * (L + L / 16) + 1) * sizeof(float2);
   return c;
 }
 
-template <int L>
-static hipError_t time_go(hipStream_t s, const float2* spec, int qb, int64_t nq, int N, int M,
-                          const float2* tw, float* D) {
-  TimeCfg c = time_cfg(L);
-  const int qpw = c.qpw;
+static bool time_twl() {
+  static const char* env = std::getenv("DDM_TIME_TWL");
+  return env == nullptr || std::atoi(env) != 0;  // default on
+}
+
+template <int L, int QPW, int QB, int E>
+static hipError_t time_go(hipStream_t s, const float2* spec, int64_t nq, int N, int M,
+                          const float2* tw, const double* ramp, float* D) {
   int64_t nwg;
-  if (qpw >= qb) {
-    nwg = (nq + qpw - 1) / qpw;
+  if (QPW >= QB) {
+    nwg = (nq + QPW - 1) / QPW;
   } else {
-    const int64_t nblocks = (nq + qb - 1) / qb;
-    nwg = ((nblocks + 7) / 8) * 8 * (qb / qpw);
+    const int64_t nblocks = (nq + QB - 1) / QB;
+    nwg = ((nblocks + 7) / 8) * 8 * (QB / QPW);
   }
   if (nwg == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_time<L, 16>), dim3((unsigned)nwg), dim3(qpw * c.T), c.lds, s, spec, qb, qpw,
-                     nq, N, M, tw, D);
+  if constexpr (QPW * (2 * L + L / 8 + 1) * 8 + L * 8 <= 163840) {
+    if (time_twl()) {
+      hipLaunchKernelGGL((k_time<L, QPW, QB, E, true>), dim3((unsigned)nwg), dim3(QPW * (L / E)), 0, s,
+                         spec, nq, N, M, tw, ramp, D);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_time<L, QPW, QB, E, false>), dim3((unsigned)nwg), dim3(QPW * (L / E)), 0, s, spec,
+                     nq, N, M, tw, ramp, D);
   return hipGetLastError();
 }
 
-hipError_t launch_time(hipStream_t s, const float2* spec, int qb, int64_t nq, int N, int M,
-                       const float2* twN2, float* D) {
+template <int L, int QPW, int E>
+static constexpr bool qpw_fits() {
+  return QPW * (L / E) <= 1024 && QPW * (2 * L + L / 8 + 1) * 8 <= 163840;
+}
+
+template <int L, int QB, int E>
+static hipError_t time_qpw_go(hipStream_t s, int qpw, const float2* spec, int64_t nq, int N, int M,
+                              const float2* tw, const double* ramp, float* D) {
+  switch (qpw) {
+    case 16: if constexpr (qpw_fits<L, 16, E>()) return time_go<L, 16, QB, E>(s, spec, nq, N, M, tw, ramp, D);
+             break;
+    case 8: if constexpr (qpw_fits<L, 8, E>()) return time_go<L, 8, QB, E>(s, spec, nq, N, M, tw, ramp, D);
+            break;
+    case 4: if constexpr (qpw_fits<L, 4, E>()) return time_go<L, 4, QB, E>(s, spec, nq, N, M, tw, ramp, D);
+            break;
+    case 2: if constexpr (qpw_fits<L, 2, E>()) return time_go<L, 2, QB, E>(s, spec, nq, N, M, tw, ramp, D);
+            break;
+    case 1: return time_go<L, 1, QB, E>(s, spec, nq, N, M, tw, ramp, D);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int L, int QB>
+static hipError_t time_e_go(hipStream_t s, const float2* spec, int64_t nq, int N, int M,
+                            const float2* tw, const double* ramp, float* D) {
+  const int E = time_e(L);
+  const int qpw = time_qpw(L, E);
+  if constexpr (L >= 512) {
+    if (E == 8) return time_qpw_go<L, QB, 8>(s, qpw, spec, nq, N, M, tw, ramp, D);
+  }
+  return time_qpw_go<L, QB, 16>(s, qpw, spec, nq, N, M, tw, ramp, D);
+}
+
+template <int QB>
+static hipError_t time_dispatch(hipStream_t s, const float2* spec, int64_t nq, int N, int M,
+                                const float2* twN2, const double* ramp, float* D) {
   int L = 16;
   while (L < N) L <<= 1;
   switch (L) {
-    case 16: return time_go<16>(s, spec, qb, nq, N, M, twN2, D);
-    case 32: return time_go<32>(s, spec, qb, nq, N, M, twN2, D);
-    case 64: return time_go<64>(s, spec, qb, nq, N, M, twN2, D);
-    case 128: return time_go<128>(s, spec, qb, nq, N, M, twN2, D);
-    case 256: return time_go<256>(s, spec, qb, nq, N, M, twN2, D);
-    case 512: return time_go<512>(s, spec, qb, nq, N, M, twN2, D);
-    case 1024: return time_go<1024>(s, spec, qb, nq, N, M, twN2, D);
-    case 2048: return time_go<2048>(s, spec, qb, nq, N, M, twN2, D);
-    case 4096: return time_go<4096>(s, spec, qb, nq, N, M, twN2, D);
+    case 16: return time_e_go<16, QB>(s, spec, nq, N, M, twN2, ramp, D);
+    case 32: return time_e_go<32, QB>(s, spec, nq, N, M, twN2, ramp, D);
+    case 64: return time_e_go<64, QB>(s, spec, nq, N, M, twN2, ramp, D);
+    case 128: return time_e_go<128, QB>(s, spec, nq, N, M, twN2, ramp, D);
+    case 256: return time_e_go<256, QB>(s, spec, nq, N, M, twN2, ramp, D);
+    case 512: return time_e_go<512, QB>(s, spec, nq, N, M, twN2, ramp, D);
+    case 1024: return time_e_go<1024, QB>(s, spec, nq, N, M, twN2, ramp, D);
+    case 2048: return time_e_go<2048, QB>(s, spec, nq, N, M, twN2, ramp, D);
+    case 4096: return time_e_go<4096, QB>(s, spec, nq, N, M, twN2, ramp, D);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_time(hipStream_t s, const float2* spec, int qb, int64_t nq, int N, int M,
+                       const float2* twN2, const double* ramp, float* D) {
+  if (qb == 1) return time_dispatch<1>(s, spec, nq, N, M, twN2, ramp, D);
+  if (qb == kSpecQB) return time_dispatch<kSpecQB>(s, spec, nq, N, M, twN2, ramp, D);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace ddm
