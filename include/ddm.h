@@ -145,6 +145,58 @@ ddm_status ddm_radial_average(ddm_plan_t plan, const float* D_dev, const int64_t
                               int32_t n_bins, double* Dbar_dev, int64_t* counts_dev,
                               int32_t* bin_of_q_dev);
 
+/* ---------------------------------------------------------------------------
+ * Fit of D(q, m) = A (1 - exp(-m / tau)) + B per wave vector (the standard DDM
+ * model; the paper computes D and leaves the fit to the analysis).
+ * ------------------------------------------------------------------------- */
+
+#define DDM_FIT_MAX_K 64
+
+/* Per-curve result flags. */
+enum {
+  DDM_FIT_CONVERGED = 1,  /* stopping test met (or stationary to precision) */
+  DDM_FIT_MAXITER = 2,    /* iteration limit reached */
+  DDM_FIT_NONFINITE = 4,  /* non-finite data or parameters */
+  DDM_FIT_STALLED = 8,    /* no decreasing step found, not stationary */
+  DDM_FIT_FALLBACK = 16   /* refitted from the default start after failing from the given one */
+};
+
+/* Sample rows of D at K fractional lags: linear interpolation between the two
+ * integer lags around each m_j, then division by the row maximum c.
+ *   D_dev [n_rows][M] float32 (device), lags_host [K] float32 in [0, M-1] (host),
+ *   1 <= K <= 64; curves_dev [n_rows][K] float32 out; scale_dev [n_rows] out
+ *   (c, or 1 when the row maximum is not positive; may be NULL).
+ * Asynchronous on `stream` (hipStream_t, NULL = default). */
+ddm_status ddm_sample_curves(const float* D_dev, int64_t n_rows, int32_t M, const float* lags_host,
+                             int32_t K, float* curves_dev, float* scale_dev, void* stream);
+
+typedef struct ddm_fit_desc {
+  uint32_t struct_size; /* = sizeof(ddm_fit_desc) */
+  int32_t K;            /* samples per curve, 1..64 */
+  int32_t max_iter;     /* Jacobian evaluations per curve (default 200) */
+  int32_t fallback;     /* 1: curves not converged from init_dev are refitted from the default start */
+  double lambda0;       /* initial Marquardt damping (default 1e-3) */
+  double ftol;          /* stop when an accepted step lowers the cost by <= ftol * cost (1e-7) */
+  double xtol;          /* stop when |step| <= xtol (|p| + xtol), p = (A, B, log tau) (1e-7) */
+  double gtol;          /* at a stall: converged if |J_i . r| <= gtol |J_i| |r| for all i (1e-3) */
+  void* stream;         /* hipStream_t */
+} ddm_fit_desc;
+
+void ddm_fit_desc_init(ddm_fit_desc* desc);
+
+/* Levenberg-Marquardt fit of every curve (one per row): minimise
+ * sum_j (A (1 - exp(-m_j / tau)) + B - y_j)^2 over (A, B, log tau) with
+ * Marquardt damping lambda diag(J^T J) (x10 on a rejected step, /10 on an
+ * accepted one); FP32 residuals, FP64 normal equations.
+ *   curves_dev [n][K] float32 (device); lags_host [K] float32 m_j > 0 (host);
+ *   init_dev [n][3] (A, B, log tau) float32 start, or NULL for the default start
+ *   (on the curve normalised by c = max_j y_j: B0 = y_1/c, A0 = 1 - B0,
+ *   tau0 = sqrt(m_1 m_K), scaled back by c);
+ *   params_dev [n][3] out (A, B, tau); iters_dev [n] (may be NULL);
+ *   flags_dev [n] DDM_FIT_* bits (required when fallback is set, else may be NULL). */
+ddm_status ddm_fit(const ddm_fit_desc* desc, const float* curves_dev, const float* lags_host, int64_t n,
+                   const float* init_dev, float* params_dev, int32_t* iters_dev, int32_t* flags_dev);
+
 /* Kernel kinds for profiling masks. */
 typedef enum ddm_kernel_kind {
   DDM_KERNEL_ROW = 1,    /* row transforms of step one */

@@ -63,6 +63,26 @@ class PlanDesc(ctypes.Structure):
     ]
 
 
+class FitDesc(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", c_uint32),
+        ("K", c_int32),
+        ("max_iter", c_int32),
+        ("fallback", c_int32),
+        ("lambda0", ctypes.c_double),
+        ("ftol", ctypes.c_double),
+        ("xtol", ctypes.c_double),
+        ("gtol", ctypes.c_double),
+        ("stream", c_void_p),
+    ]
+
+
+DDM_FIT_CONVERGED = 1
+DDM_FIT_MAXITER = 2
+DDM_FIT_NONFINITE = 4
+DDM_FIT_STALLED = 8
+DDM_FIT_FALLBACK = 16
+
 # (name, restype, argtypes) for every symbol of include/ddm.h
 SIGNATURES = [
     ("ddm_plan_desc_init", None, [P(PlanDesc)]),
@@ -79,6 +99,10 @@ SIGNATURES = [
      [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     ("ddm_plan_set_profiling", c_int32, [c_void_p, c_uint32]),
     ("ddm_plan_get_profile", c_int32, [c_void_p, c_uint32, P(ctypes.c_double), P(c_int64)]),
+    ("ddm_sample_curves", c_int32,
+     [c_void_p, c_int64, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    ("ddm_fit_desc_init", None, [P(FitDesc)]),
+    ("ddm_fit", c_int32, [P(FitDesc), c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("ddm_last_error", ctypes.c_char_p, []),
     ("ddm_abi_version", c_int32, []),
 ]

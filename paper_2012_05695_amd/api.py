@@ -223,6 +223,55 @@ class Plan:
         return Dbar, counts, boq
 
 
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def log_lags(n_frames, K=64):
+    """K log-spaced fractional lags from 1 to N-1 (float32)."""
+    return np.geomspace(1.0, float(n_frames - 1), K).astype(np.float32)
+
+
+def sample_curves(D, lags, stream=None):
+    """Rows of D [n, M] sampled at fractional lags -> (curves [n, K] / row max, scale [n])."""
+    lags = np.ascontiguousarray(np.asarray(lags, dtype=np.float32))
+    n, M = D.shape
+    _require(D, "D", (torch.float32,), (n, M), None)
+    K = len(lags)
+    curves = torch.empty((n, K), dtype=torch.float32, device=D.device)
+    scale = torch.empty((n,), dtype=torch.float32, device=D.device)
+    with torch.cuda.device(D.device):
+        _check(_lib.ddm_sample_curves(_ptr(D), n, M, ctypes.c_void_p(lags.ctypes.data), K, _ptr(curves),
+                                      _ptr(scale), _stream_handle(stream)))
+    return curves, scale
+
+
+def fit(curves, lags, init=None, fallback=True, max_iter=200, ftol=1e-7, xtol=1e-7, gtol=1e-3,
+        lambda0=1e-3, stream=None):
+    """LM fit of every row of curves [n, K] -> (params [n, 3] = A, B, tau; iters [n]; flags [n]).
+
+    init: optional [n, 3] float32 (A, B, log tau) start; else the default start.
+    """
+    lags = np.ascontiguousarray(np.asarray(lags, dtype=np.float32))
+    n, K = curves.shape
+    _require(curves, "curves", (torch.float32,), (n, K), None)
+    if init is not None:
+        _require(init, "init", (torch.float32,), (n, 3), None)
+    d = L.FitDesc()
+    _lib.ddm_fit_desc_init(ctypes.byref(d))
+    d.K, d.max_iter, d.fallback = K, int(max_iter), 1 if fallback else 0
+    d.ftol, d.xtol, d.gtol, d.lambda0 = float(ftol), float(xtol), float(gtol), float(lambda0)
+    with torch.cuda.device(curves.device):
+        d.stream = _stream_handle(stream).value
+    params = torch.empty((n, 3), dtype=torch.float32, device=curves.device)
+    iters = torch.empty((n,), dtype=torch.int32, device=curves.device)
+    flags = torch.empty((n,), dtype=torch.int32, device=curves.device)
+    with torch.cuda.device(curves.device):
+        _check(_lib.ddm_fit(ctypes.byref(d), _ptr(curves), ctypes.c_void_p(lags.ctypes.data), n, _ptr(init),
+                            _ptr(params), _ptr(iters), _ptr(flags)))
+    return params, iters, flags
+
+
 def integer_bin_thresholds(n_bins):
     """Thresholds of the bins b = round(|k|), b = 0..n_bins-1, on integer k2.
 

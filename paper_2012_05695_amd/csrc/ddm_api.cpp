@@ -498,4 +498,75 @@ ddm_status ddm_plan_get_profile(ddm_plan_t p, uint32_t kind, double* total_ms, i
   return DDM_OK;
 }
 
+static ddm_status fill_lags(const float* lags, int32_t K, float lo, float hi, LagSet* out) {
+  if (lags == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "lags is NULL");
+  if (K < 1 || K > DDM_FIT_MAX_K) return fail(DDM_ERR_INVALID_ARGUMENT, "K must be in [1, 64]");
+  out->K = K;
+  for (int j = 0; j < DDM_FIT_MAX_K; ++j) out->m[j] = 0.f;
+  for (int j = 0; j < K; ++j) {
+    const float m = lags[j];
+    if (!std::isfinite(m) || m < lo || m > hi)
+      return fail(DDM_ERR_INVALID_ARGUMENT, "lag %d = %g outside [%g, %g]", j, (double)m, (double)lo, (double)hi);
+    out->m[j] = m;
+  }
+  return DDM_OK;
+}
+
+ddm_status ddm_sample_curves(const float* D, int64_t n_rows, int32_t M, const float* lags, int32_t K,
+                             float* curves, float* scale, void* stream) {
+  if (D == nullptr || curves == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "D/curves is NULL");
+  if (n_rows < 0) return fail(DDM_ERR_INVALID_ARGUMENT, "n_rows must be >= 0");
+  if (M < 2) return fail(DDM_ERR_INVALID_ARGUMENT, "M must be >= 2");
+  LagSet ls;
+  ddm_status st = fill_lags(lags, K, 0.f, (float)(M - 1), &ls);
+  if (st != DDM_OK) return st;
+  hipError_t e = launch_sample((hipStream_t)stream, D, n_rows, M, ls, curves, scale);
+  if (e != hipSuccess) return hip_fail(e, "curve sampling launch");
+  return DDM_OK;
+}
+
+void ddm_fit_desc_init(ddm_fit_desc* d) {
+  if (d == nullptr) return;
+  std::memset(d, 0, sizeof(*d));
+  d->struct_size = sizeof(ddm_fit_desc);
+  d->K = 64;
+  d->max_iter = 200;
+  d->fallback = 1;
+  d->lambda0 = 1e-3;
+  d->ftol = 1e-7;
+  d->xtol = 1e-7;
+  d->gtol = 1e-3;
+  d->stream = nullptr;
+}
+
+ddm_status ddm_fit(const ddm_fit_desc* f, const float* curves, const float* lags, int64_t n, const float* init,
+                   float* params, int32_t* iters, int32_t* flags) {
+  if (f == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "desc is NULL");
+  if (f->struct_size != sizeof(ddm_fit_desc))
+    return fail(DDM_ERR_INVALID_ARGUMENT, "desc.struct_size %u != %zu", f->struct_size, sizeof(ddm_fit_desc));
+  if (curves == nullptr || params == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "curves/params is NULL");
+  if (n < 0) return fail(DDM_ERR_INVALID_ARGUMENT, "n must be >= 0");
+  if (f->max_iter < 1) return fail(DDM_ERR_INVALID_ARGUMENT, "max_iter must be >= 1");
+  if (!(f->lambda0 > 0) || !(f->ftol >= 0) || !(f->xtol >= 0) || !(f->gtol >= 0))
+    return fail(DDM_ERR_INVALID_ARGUMENT, "lambda0 must be > 0 and tolerances >= 0");
+  const bool fb = init != nullptr && f->fallback != 0;
+  if (fb && flags == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "fallback needs flags_dev");
+  LagSet ls;
+  ddm_status st = fill_lags(lags, f->K, 1e-30f, 3.0e38f, &ls);
+  if (st != DDM_OK) return st;
+  LmParams prm;
+  prm.lambda0 = f->lambda0;
+  prm.lambda_max = 1e16;
+  prm.ftol = f->ftol;
+  prm.xtol = f->xtol;
+  prm.gtol = f->gtol;
+  prm.exact_fit = 1e-12;  // relative cost floor of FP32 residuals
+  prm.max_iter = f->max_iter;
+  hipStream_t s = (hipStream_t)f->stream;
+  hipError_t e = launch_lm(s, curves, n, ls, init, prm, nullptr, params, iters, flags);
+  if (e == hipSuccess && fb) e = launch_lm(s, curves, n, ls, nullptr, prm, flags, params, iters, flags);
+  if (e != hipSuccess) return hip_fail(e, "fit launch");
+  return DDM_OK;
+}
+
 }  // extern "C"

@@ -49,6 +49,25 @@ struct QTable {
 
 bool supported_spatial(int n);
 
+// Fractional lags of the fit (at most 64), passed by value to the kernels.
+struct LagSet {
+  int K;
+  float m[64];
+};
+
+struct LmParams {
+  double lambda0, lambda_max, ftol, xtol, gtol, exact_fit;
+  int max_iter;
+};
+
+enum : int32_t {
+  LM_FLAG_CONVERGED = 1,
+  LM_FLAG_MAXITER = 2,
+  LM_FLAG_NONFINITE = 4,
+  LM_FLAG_STALLED = 8,
+  LM_FLAG_FALLBACK = 16
+};
+
 // ---- launchers (each returns hipSuccess or the launch error) ----
 hipError_t launch_row(hipStream_t s, int pixel, const void* frames, int W, int H, int64_t t0,
                       int nframes, int precondition, float2* inter, int kxw,
@@ -64,5 +83,12 @@ hipError_t launch_time(hipStream_t s, const float2* spec, int qb, int64_t nq_gro
 hipError_t launch_radial(hipStream_t s, const float* D, int64_t nq, int M, int W, int H,
                          int64_t ca, int64_t cc, QTable qt, const int64_t* thr, int nbins,
                          double* Dbar, int64_t* counts, int32_t* bin_of_q);
+
+hipError_t launch_sample(hipStream_t s, const float* D, int64_t n, int M, const LagSet& lags, float* Y,
+                         float* scale);
+
+hipError_t launch_lm(hipStream_t s, const float* Y, int64_t n, const LagSet& lags, const float* init,
+                     const LmParams& prm, const int32_t* only_if_flag_clear, float* params,
+                     int32_t* iters, int32_t* flags);
 
 }  // namespace ddm

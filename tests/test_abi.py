@@ -46,19 +46,21 @@ def test_binding_covers_every_declared_symbol(libddm_path):
     _lib.load(libddm_path)
 
 
-def test_plan_desc_layout_matches_c(tmp_path):
+@pytest.mark.parametrize("cname,pyname", [("ddm_plan_desc", "PlanDesc"), ("ddm_fit_desc", "FitDesc")])
+def test_struct_layout_matches_c(tmp_path, cname, pyname):
     from paper_2012_05695_amd import _lib
+    cls = getattr(_lib, pyname)
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "ddm.h"\n'
-        "int main(void){printf(\"%zu\", sizeof(ddm_plan_desc));"
-        + "".join('printf(" %%zu", offsetof(ddm_plan_desc, %s));' % f for f, _ in _lib.PlanDesc._fields_)
+        "int main(void){printf(\"%%zu\", sizeof(%s));" % cname
+        + "".join('printf(" %%zu", offsetof(%s, %s));' % (cname, f) for f, _ in cls._fields_)
         + "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     vals = [int(x) for x in subprocess.check_output([str(exe)]).split()]
-    assert vals[0] == ctypes.sizeof(_lib.PlanDesc)
-    offs = [getattr(_lib.PlanDesc, f).offset for f, _ in _lib.PlanDesc._fields_]
+    assert vals[0] == ctypes.sizeof(cls)
+    offs = [getattr(cls, f).offset for f, _ in cls._fields_]
     assert vals[1:] == offs
 
 

@@ -1,0 +1,85 @@
+"""GPU curve sampling and Levenberg-Marquardt fit against the FP64 oracle."""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import lm
+from paper_2012_05695_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def test_sample_curves(gpu):
+    say("case: sample curves")
+    r = np.random.default_rng(0)
+    D = np.abs(r.standard_normal((300, 500))).astype(np.float32) * 10
+    D[7] = 0.0
+    lags = lm.log_lags(500)
+    cg, sg = gpu.sample_curves(torch.from_numpy(D).cuda(), lags)
+    co, so = lm.sample_curves(D, lags)
+    np.testing.assert_allclose(sg.cpu().numpy(), so, rtol=1e-6)
+    np.testing.assert_allclose(cg.cpu().numpy(), co, rtol=2e-6, atol=1e-7)
+
+
+def synth_curves(n, K=64, N=2048, noise=0.0, seed=0):
+    r = np.random.default_rng(seed)
+    m = lm.log_lags(N, K).astype(np.float64)
+    A = r.uniform(0.3, 1.0, n)
+    B = r.uniform(0.0, 0.5, n)
+    tau = np.exp(r.uniform(np.log(2.0), np.log(0.5 * N), n))
+    Y = A[:, None] * (1 - np.exp(-m[None, :] / tau[:, None])) + B[:, None]
+    Y = Y * (1 + noise * r.standard_normal(Y.shape))
+    return Y.astype(np.float32), np.stack([A, B, tau], 1), m.astype(np.float32)
+
+
+def test_lm_noise_free_recovery(gpu):
+    say("case: LM noise-free")
+    Y, P, m = synth_curves(2000)
+    params, iters, flags = gpu.fit(torch.from_numpy(Y).cuda(), m)
+    params, flags = params.cpu().numpy(), flags.cpu().numpy()
+    conv = (flags & 1) != 0
+    say("converged %.4f, median iters %d" % (conv.mean(), np.median(iters.cpu().numpy())))
+    assert conv.mean() >= 0.995
+    rel = np.abs(params[conv] - P[conv]) / np.abs(P[conv]).clip(1e-3)
+    assert np.percentile(rel, 99) < 1e-3
+
+
+def test_lm_matches_oracle_on_noisy_curves(gpu):
+    say("case: LM noisy vs oracle")
+    Y, P, m = synth_curves(400, noise=0.02, seed=3)
+    params, iters, flags = gpu.fit(torch.from_numpy(Y).cuda(), m)
+    params, flags = params.cpu().numpy(), flags.cpu().numpy()
+    Po, Co, Io, Fo = lm.lm_fit_many(Y.astype(np.float64), m.astype(np.float64))
+    mm = m.astype(np.float64)
+    cost_g = np.array([np.sum((lm.model((p[0], p[1], np.log(p[2])), mm) - y) ** 2)
+                       for p, y in zip(params.astype(np.float64), Y.astype(np.float64))])
+    both = ((flags & 1) != 0) & ((Fo & 1) != 0)
+    say("both converged %.4f" % both.mean())
+    assert both.mean() >= 0.98
+    excess = (cost_g[both] - Co[both]) / Co[both]
+    say("cost excess max %.3e" % excess.max())
+    assert excess.max() < 1e-4
+    tau_o = np.exp(Po[both, 2])
+    assert np.percentile(np.abs(params[both, 2] - tau_o) / tau_o, 95) < 1e-2
+
+
+def test_fit_init_and_fallback(gpu):
+    say("case: LM init + fallback")
+    Y, P, m = synth_curves(256, noise=0.01, seed=5)
+    good = torch.from_numpy(np.stack([P[:, 0], P[:, 1], np.log(P[:, 2])], 1).astype(np.float32)).cuda()
+    pa, ia, fa = gpu.fit(torch.from_numpy(Y).cuda(), m, init=good)
+    pd, id_, fd = gpu.fit(torch.from_numpy(Y).cuda(), m)
+    assert ia.float().mean() < id_.float().mean()      # a good start saves iterations
+    bad = good.clone()
+    bad[:10] = float("nan")                              # poisoned starts -> default-start refit
+    pb, ib, fb = gpu.fit(torch.from_numpy(Y).cuda(), m, init=bad)
+    fb = fb.cpu().numpy()
+    assert np.all(fb[:10] & 16) and np.all(fb[:10] & 1)
+    assert not np.any(fb[10:] & 16)
