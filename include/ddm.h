@@ -197,6 +197,63 @@ void ddm_fit_desc_init(ddm_fit_desc* desc);
 ddm_status ddm_fit(const ddm_fit_desc* desc, const float* curves_dev, const float* lags_host, int64_t n,
                    const float* init_dev, float* params_dev, int32_t* iters_dev, int32_t* flags_dev);
 
+/* ---------------------------------------------------------------------------
+ * Fit-initialisation network (not in the paper): a normalised curve of
+ * DDM_MLP_IN samples (ddm_sample_curves at log-spaced lags) -> 3 x
+ * [Linear(256), GELU] -> Linear(3) = a start (A, B, log tau) for ddm_fit, in
+ * the units of the normalised curve (targets are standardised by the caller).
+ * BF16 matrix-core products with FP32 accumulation; FP32 master parameters
+ * and Adam state.  Parameter vector layout (DDM_MLP_NPARAMS floats, row-major,
+ * W[o][i] maps input i to output o): W1[256][64] b1[256] W2[256][256] b2[256]
+ * W3[256][256] b3[256] W4[3][256] b4[3].  GELU is exact: z Phi(z).
+ * Loss: mean squared error over the batch and the 3 outputs.
+ * ------------------------------------------------------------------------- */
+
+#define DDM_MLP_IN 64
+#define DDM_MLP_HIDDEN 256
+#define DDM_MLP_OUT 3
+#define DDM_MLP_NPARAMS 148995
+
+typedef struct ddm_mlp_s* ddm_mlp_t;
+
+/* Create a network with parameters uniform in +-1/sqrt(fan_in) from `seed`
+ * and device buffers for batches of up to max_batch rows (about
+ * max_batch * 5.6 KB plus 2.7 MB).  All work runs on `stream` (hipStream_t). */
+ddm_status ddm_mlp_create(uint64_t seed, int64_t max_batch, void* stream, ddm_mlp_t* out);
+ddm_status ddm_mlp_destroy(ddm_mlp_t mlp);
+
+/* Host copies of the FP32 parameters (DDM_MLP_NPARAMS floats).  set_params
+ * also clears the Adam state (step 0).  Both synchronise the stream. */
+ddm_status ddm_mlp_set_params(ddm_mlp_t mlp, const float* params_host);
+ddm_status ddm_mlp_get_params(ddm_mlp_t mlp, float* params_host);
+
+/* Full training state (parameters, Adam moments, step count) for checkpoints:
+ * three host arrays of DDM_MLP_NPARAMS floats.  Synchronises the stream. */
+ddm_status ddm_mlp_get_state(ddm_mlp_t mlp, float* params_host, float* adam_m_host, float* adam_v_host,
+                             int64_t* step);
+ddm_status ddm_mlp_set_state(ddm_mlp_t mlp, const float* params_host, const float* adam_m_host,
+                             const float* adam_v_host, int64_t step);
+
+/* Inference: x_dev [rows][64] float32 -> y_dev [rows][3] float32 (any rows;
+ * processed in chunks of max_batch).  Asynchronous. */
+ddm_status ddm_mlp_forward(ddm_mlp_t mlp, const float* x_dev, int64_t rows, float* y_dev);
+
+/* Forward + backward on one batch (1 <= B <= max_batch): keeps the gradient
+ * on the device for ddm_mlp_adam_step; if grad_host / loss_host are non-NULL
+ * the call synchronises and copies the gradient (DDM_MLP_NPARAMS floats) and
+ * the loss out. */
+ddm_status ddm_mlp_gradient(ddm_mlp_t mlp, const float* x_dev, const float* target_dev, int64_t B,
+                            float* grad_host, float* loss_host);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the
+ * last gradient. */
+ddm_status ddm_mlp_adam_step(ddm_mlp_t mlp, float lr);
+
+/* ddm_mlp_gradient + ddm_mlp_adam_step without host synchronisation; the
+ * batch loss is written to loss_dev (device float, may be NULL). */
+ddm_status ddm_mlp_train_step(ddm_mlp_t mlp, const float* x_dev, const float* target_dev, int64_t B, float lr,
+                              float* loss_dev);
+
 /* Kernel kinds for profiling masks. */
 typedef enum ddm_kernel_kind {
   DDM_KERNEL_ROW = 1,    /* row transforms of step one */

@@ -118,3 +118,21 @@ def load(path=LIB_PATH):
         fn.restype = res
         fn.argtypes = args
     return lib
+
+DDM_MLP_IN = 64
+DDM_MLP_HIDDEN = 256
+DDM_MLP_OUT = 3
+DDM_MLP_NPARAMS = 148995
+
+SIGNATURES += [
+    ("ddm_mlp_create", c_int32, [ctypes.c_uint64, c_int64, c_void_p, P(c_void_p)]),
+    ("ddm_mlp_destroy", c_int32, [c_void_p]),
+    ("ddm_mlp_set_params", c_int32, [c_void_p, c_void_p]),
+    ("ddm_mlp_get_params", c_int32, [c_void_p, c_void_p]),
+    ("ddm_mlp_get_state", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, P(c_int64)]),
+    ("ddm_mlp_set_state", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64]),
+    ("ddm_mlp_forward", c_int32, [c_void_p, c_void_p, c_int64, c_void_p]),
+    ("ddm_mlp_gradient", c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
+    ("ddm_mlp_adam_step", c_int32, [c_void_p, ctypes.c_float]),
+    ("ddm_mlp_train_step", c_int32, [c_void_p, c_void_p, c_void_p, c_int64, ctypes.c_float, c_void_p]),
+]

@@ -297,3 +297,86 @@ def log_bin_thresholds(n_bins, k_min, k_max):
     if np.any(np.diff(t) <= 0):
         raise ValueError("log bins collapse at low k; raise k_min or lower n_bins")
     return t
+
+
+class Mlp:
+    """The fit-initialisation network (ddm_mlp_* of include/ddm.h)."""
+
+    N_PARAMS = L.DDM_MLP_NPARAMS
+
+    def __init__(self, seed=0, max_batch=4096, stream=None, device=None):
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        self.max_batch = int(max_batch)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.ddm_mlp_create(int(seed), self.max_batch, _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self.loss_dev = torch.zeros(1, dtype=torch.float32, device="cuda:%d" % self.device)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            with torch.cuda.device(self.device):
+                _check(_lib.ddm_mlp_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        p = np.empty(self.N_PARAMS, dtype=np.float32)
+        _check(_lib.ddm_mlp_get_params(self._h, ctypes.c_void_p(p.ctypes.data)))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(np.asarray(p, dtype=np.float32))
+        assert p.shape == (self.N_PARAMS,)
+        _check(_lib.ddm_mlp_set_params(self._h, ctypes.c_void_p(p.ctypes.data)))
+
+    def get_state(self):
+        p, m, v = (np.empty(self.N_PARAMS, dtype=np.float32) for _ in range(3))
+        st = ctypes.c_int64()
+        _check(_lib.ddm_mlp_get_state(self._h, ctypes.c_void_p(p.ctypes.data), ctypes.c_void_p(m.ctypes.data),
+                                      ctypes.c_void_p(v.ctypes.data), ctypes.byref(st)))
+        return {"params": p, "adam_m": m, "adam_v": v, "step": int(st.value)}
+
+    def set_state(self, s):
+        p, m, v = (np.ascontiguousarray(np.asarray(s[k], dtype=np.float32)) for k in ("params", "adam_m", "adam_v"))
+        _check(_lib.ddm_mlp_set_state(self._h, ctypes.c_void_p(p.ctypes.data), ctypes.c_void_p(m.ctypes.data),
+                                      ctypes.c_void_p(v.ctypes.data), int(s["step"])))
+
+    def forward(self, x, out=None):
+        n = x.shape[0]
+        _require(x, "x", (torch.float32,), (n, L.DDM_MLP_IN), self.device)
+        if out is None:
+            out = torch.empty((n, L.DDM_MLP_OUT), dtype=torch.float32, device=x.device)
+        with torch.cuda.device(self.device):
+            _check(_lib.ddm_mlp_forward(self._h, _ptr(x), n, _ptr(out)))
+        return out
+
+    def gradient(self, x, t):
+        """(grad [N_PARAMS] float32 numpy, loss) for one batch (host sync)."""
+        B = x.shape[0]
+        _require(x, "x", (torch.float32,), (B, L.DDM_MLP_IN), self.device)
+        _require(t, "t", (torch.float32,), (B, L.DDM_MLP_OUT), self.device)
+        g = np.empty(self.N_PARAMS, dtype=np.float32)
+        loss = ctypes.c_float()
+        with torch.cuda.device(self.device):
+            _check(_lib.ddm_mlp_gradient(self._h, _ptr(x), _ptr(t), B, ctypes.c_void_p(g.ctypes.data),
+                                         ctypes.byref(loss)))
+        return g, float(loss.value)
+
+    def adam_step(self, lr):
+        _check(_lib.ddm_mlp_adam_step(self._h, float(lr)))
+
+    def train_step(self, x, t, lr):
+        """One asynchronous step; the batch loss lands in self.loss_dev."""
+        B = x.shape[0]
+        _require(x, "x", (torch.float32,), (B, L.DDM_MLP_IN), self.device)
+        _require(t, "t", (torch.float32,), (B, L.DDM_MLP_OUT), self.device)
+        with torch.cuda.device(self.device):
+            _check(_lib.ddm_mlp_train_step(self._h, _ptr(x), _ptr(t), B, float(lr), _ptr(self.loss_dev)))

@@ -27,7 +27,8 @@ COMMON = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 
-SOURCES = ["ddm_api.cpp", "k_spatial.hip", "k_time.hip", "k_radial.hip"]
+SOURCES = ["ddm_api.cpp", "mlp_api.cpp", "k_spatial.hip", "k_time.hip", "k_radial.hip", "k_fit.hip",
+           "k_mlp.hip"]
 
 
 def _sources():

@@ -37,6 +37,23 @@ ddm_status hip_fail(hipError_t e, const char* what) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+}  // namespace
+
+namespace ddm {
+// error reporting shared with the other ABI translation units
+ddm_status api_fail(ddm_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+}  // namespace ddm
+
+namespace {
+
 constexpr size_t kInterTargetBytes = 64u << 20;  // row-transform intermediate per batch
 
 }  // namespace
