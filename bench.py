@@ -33,6 +33,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-columns", type=int, default=64,
                     help="kx columns of the oracle sample (all ky, all frames, all lags)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the tau-fit leg (network training + LM vs MLP+LM on 1024x1024x2048)")
+    ap.add_argument("--learned-curves", type=int, default=1_000_000)
+    ap.add_argument("--learned-epochs", type=int, default=30)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (HBM byte-counter calibration)")
     ap.add_argument("--kernel-only", default=None,
@@ -73,6 +77,37 @@ def cpu_baseline(frames_cpu, ncols, nq_total):
             "sample": "kx columns 0..%d x all %d ky (%d of %d q), all %d frames and lags; "
                       "%.2f s measured, extrapolated linearly in q to %.0f s" %
                       (ncols - 1, H, nq_s, nq_total, N, dt, full_s)}
+
+
+def learned_leg(log):
+    """tau-fit time of MLP+LM against LM from the default start, on every q of a
+    1024x1024x2048 stack; the network is trained first on curves computed by
+    the pipeline from 128x128x2048 stacks (D0 and SNR log-uniform)."""
+    import numpy as np
+    import torch
+    from paper_2012_05695_amd import learn
+
+    args = parse()
+    t0 = time.perf_counter()
+    X, T, lags = learn.make_training_set(args.learned_curves, W=128, H=128, N=2048, seed0=1000)
+    t1 = time.perf_counter()
+    init, losses = learn.train(X, T, epochs=args.learned_epochs, batch=4096, lr=2e-3)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    del X, T
+    rng = np.random.default_rng(7)
+    D0, snr, n_spots, a = learn.draw_stack_params(rng, 1024, 1024)
+    curves, scale, (A, B, tau) = learn.stack_curves(1024, 1024, 2048, D0, n_spots, a, 7, lags)
+    learn.compare(curves[:4096].contiguous(), lags, init)  # warm-up
+    res = learn.compare(curves, lags, init, truth_tau=tau, tau_window=(2.0, 512.0))
+    log("learned leg: data %.1f s, training %.1f s (loss %.3f -> %.3f)" %
+        (t1 - t0, t2 - t1, losses[0], losses[-1]))
+    return {"stack": "1024x1024 uint16 x 2048 frames, D0 %.3g px^2/frame, SNR %.3g, seed 7" % (D0, snr),
+            "n_curves": res["n"], "K": 64,
+            "lm_default_ms": res["default_ms"], "mlp_plus_lm_ms": res["learned_ms"],
+            "all": res["all"], "measurable_tau_2_to_512": res.get("measurable"),
+            "training": {"curves": args.learned_curves, "epochs": args.learned_epochs,
+                         "final_loss": losses[-1], "data_s": t1 - t0, "train_s": t2 - t1}}
 
 
 def main():
@@ -160,7 +195,7 @@ def main():
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
 
     out = {
-        "metric": "frames/s for D(q,dt) at 512x512x1024 (whole path incl. radial average)",
+        "metric": "frames/s & % HBM peak for D(q,dt) at 512x512x1024; tau-fit time MLP+LM vs LM",
         "value": N / (ms_step * 1e-3),
         "unit": "frames/s",
         "n_gpus": 1,
@@ -184,9 +219,17 @@ def main():
                      "avg_launch_ms": avg_launch_ms, "launches": k_n,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }
-    if not args.no_cpu_baseline:
+    frames_cpu = frames.cpu() if not args.no_cpu_baseline else None
+    del frames, D
+    plan.close()
+    torch.cuda.empty_cache()
+    if not args.no_learned:
+        print("bench: tau-fit leg (training the start network, then LM vs MLP+LM)", file=sys.stderr,
+              flush=True)
+        out["tau_fit"] = learned_leg(lambda m: print("bench: " + m, file=sys.stderr, flush=True))
+    if frames_cpu is not None:
         print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(frames.cpu(), args.cpu_columns, nq)
+        out["cpu_baseline"] = cpu_baseline(frames_cpu, args.cpu_columns, nq)
     print(json.dumps(out), flush=True)
 
 

@@ -59,8 +59,11 @@ typedef enum ddm_status {
 typedef enum ddm_pixel { DDM_PIX_U8 = 1, DDM_PIX_U16 = 2 } ddm_pixel;
 
 /* Storage of the per-wave-vector time series between step one and step two.
- * F32: complex FP32.  F16_QSCALED: complex FP16 with a per-q power-of-two scale
- * chosen from pilot frames, halving the spectrum traffic. */
+ * F32: complex FP32.  F16_QSCALED: complex FP16, each wave vector scaled by a
+ * power of two 2^e(q) (exact) chosen so that the largest component over the
+ * pilot frames {floor(jN/8), j = 1..7} and N-1 falls in (2^10, 2^11] (a factor
+ * 32 below the FP16 maximum); components beyond 65504 are clipped and counted.
+ * Halves the spectrum traffic; D within 5e-3 of the FP32 result's accuracy. */
 typedef enum ddm_spectrum { DDM_SPEC_F32 = 0, DDM_SPEC_F16_QSCALED = 1 } ddm_spectrum;
 
 typedef struct ddm_plan_s* ddm_plan_t;
@@ -121,6 +124,10 @@ ddm_status ddm_plan_set_workspace(ddm_plan_t plan, void* workspace_dev, size_t b
  * the FP16 spectrum store clipped values. */
 ddm_status ddm_structure_function(ddm_plan_t plan, const void* frames_dev, float* D_dev);
 
+/* FP16 spectrum store: total number of spectrum components clipped to
+ * +-65504 since the plan was created (waits for the last call's count). */
+ddm_status ddm_plan_fp16_saturations(ddm_plan_t plan, int64_t* count);
+
 /* Step one only: frames_dev [N][H][W] -> spectra_dev [n_q][N] complex float32
  * (interleaved re, im; q order, time contiguous), the 2-D transforms F(q, t)
  * of the frames, or of I_t - I_0 when the plan preconditions.  Requires a
@@ -132,10 +139,44 @@ ddm_status ddm_image_spectra(ddm_plan_t plan, const void* frames_dev, float* spe
  * Needs no workspace. */
 ddm_status ddm_structure_from_spectra(ddm_plan_t plan, const float* spectra_dev, float* D_dev);
 
+/* Pick the time-kernel launch shape (values per thread, wave vectors per
+ * workgroup) for this plan by timing the candidates on zero-filled spectra in
+ * the plan's workspace (required); the choice is cached per (time length, N,
+ * max_lag, storage) for the process and used by later calls.  Synchronises
+ * the stream.  DDM_AUTOTUNE=off (environment) keeps the built-in shape.
+ * Outputs (may be NULL): E, wave vectors per workgroup, estimated ms per call. */
+ddm_status ddm_plan_autotune(ddm_plan_t plan, int32_t* E, int32_t* qpw, double* ms);
+
+/* ---------------------------------------------------------------------------
+ * Batches of independent stacks of uneven sizes (many regions of interest or
+ * stacks at once).  One plan per stack (FP32 spectra); stacks are spread over
+ * `lanes` internal streams, largest first onto the least loaded one; each
+ * lane owns a slice of the caller's workspace, reused by its stacks in turn.
+ * The first call (and any call with different pointers) captures the whole
+ * fork/join sequence into a HIP graph; every call is one graph launch on
+ * `stream`.  Results per stack equal ddm_structure_function bit for bit.
+ * ------------------------------------------------------------------------- */
+typedef struct ddm_batch_s* ddm_batch_t;
+
+ddm_status ddm_batch_create(const ddm_plan_desc* descs, int32_t n_stacks, int32_t lanes, void* stream,
+                            ddm_batch_t* out);
+ddm_status ddm_batch_destroy(ddm_batch_t batch);
+/* rows of D (n_q) and lags (max_lag) of one stack, and the lane it runs on */
+ddm_status ddm_batch_query(ddm_batch_t batch, int32_t stack, int64_t* n_q, int32_t* max_lag, int32_t* lane);
+ddm_status ddm_batch_workspace_size(ddm_batch_t batch, size_t* bytes);
+ddm_status ddm_batch_set_workspace(ddm_batch_t batch, void* workspace_dev, size_t bytes);
+/* ddm_plan_autotune for every stack (needs the workspace). */
+ddm_status ddm_batch_autotune(ddm_batch_t batch);
+/* frames_dev[i] [N_i][H_i][W_i] -> D_dev[i] [n_q_i][M_i]; both arrays are host
+ * arrays of n_stacks device pointers. */
+ddm_status ddm_batch_structure_function(ddm_batch_t batch, const void* const* frames_dev,
+                                        float* const* D_dev);
+
 /* Azimuthal average of D over |q| bins (standard DDM reduction; not in the
  * paper).  Bin b holds the kept q with T[b] <= k2 < T[b+1], T =
- * k2_thresholds_host[0..n_bins] (strictly increasing int64, host); others are
- * unbinned.  Weight w(q) = 2 for 0 < kx < W/2 (q stands for q and -q), else 1.
+ * k2_thresholds_host[0..n_bins] (non-decreasing int64 >= 0, host; equal
+ * neighbours make an empty bin); other q are unbinned.
+ * Weight w(q) = 2 for 0 < kx < W/2 (q stands for q and -q), else 1.
  *   Dbar_dev [n_bins][M] float64: sum w D / sum w   (0 for an empty bin)
  *   counts_dev [n_bins] int64:     sum w            (full-plane lattice points)
  *   bin_of_q_dev [n_q] int32:      bin of each row of D, -1 if unbinned (may be NULL)

@@ -11,7 +11,7 @@ raise if it is missing; ``synth`` (seeded input stacks) needs no library.
 """
 
 _API = {"Plan", "DdmError", "integer_bin_thresholds", "log_bin_thresholds", "abi_version",
-        "last_error", "log_lags", "sample_curves", "fit", "Mlp"}
+        "last_error", "log_lags", "sample_curves", "fit", "Mlp", "Batch"}
 
 
 def __getattr__(name):

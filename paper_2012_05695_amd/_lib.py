@@ -97,6 +97,7 @@ SIGNATURES = [
     ("ddm_structure_from_spectra", c_int32, [c_void_p, c_void_p, c_void_p]),
     ("ddm_radial_average", c_int32,
      [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    ("ddm_plan_fp16_saturations", c_int32, [c_void_p, P(c_int64)]),
     ("ddm_plan_set_profiling", c_int32, [c_void_p, c_uint32]),
     ("ddm_plan_get_profile", c_int32, [c_void_p, c_uint32, P(ctypes.c_double), P(c_int64)]),
     ("ddm_sample_curves", c_int32,
@@ -135,4 +136,15 @@ SIGNATURES += [
     ("ddm_mlp_gradient", c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
     ("ddm_mlp_adam_step", c_int32, [c_void_p, ctypes.c_float]),
     ("ddm_mlp_train_step", c_int32, [c_void_p, c_void_p, c_void_p, c_int64, ctypes.c_float, c_void_p]),
+]
+
+SIGNATURES += [
+    ("ddm_plan_autotune", c_int32, [c_void_p, P(c_int32), P(c_int32), P(ctypes.c_double)]),
+    ("ddm_batch_create", c_int32, [P(PlanDesc), c_int32, c_int32, c_void_p, P(c_void_p)]),
+    ("ddm_batch_destroy", c_int32, [c_void_p]),
+    ("ddm_batch_query", c_int32, [c_void_p, c_int32, P(c_int64), P(c_int32), P(c_int32)]),
+    ("ddm_batch_workspace_size", c_int32, [c_void_p, P(c_size_t)]),
+    ("ddm_batch_set_workspace", c_int32, [c_void_p, c_void_p, c_size_t]),
+    ("ddm_batch_autotune", c_int32, [c_void_p]),
+    ("ddm_batch_structure_function", c_int32, [c_void_p, c_void_p, c_void_p]),
 ]

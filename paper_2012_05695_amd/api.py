@@ -97,6 +97,7 @@ class Plan:
         _check(_lib.ddm_plan_query(h, ctypes.byref(nq), ctypes.byref(ml), ctypes.byref(n2)))
         self.n_q, self.max_lag, self.n2 = int(nq.value), int(ml.value), int(n2.value)
         self._ws = None
+        self.last_status = L.DDM_OK
 
     # -- lifetime --
     def close(self):
@@ -146,6 +147,15 @@ class Plan:
         self.set_workspace(ws)
         return ws
 
+    def autotune(self):
+        """Time the time-kernel launch shapes on this plan's workspace; returns (E, qpw, ms)."""
+        if self._ws is None:
+            self.allocate_workspace()
+        E, q, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        with torch.cuda.device(self.device):
+            _check(_lib.ddm_plan_autotune(self._h, ctypes.byref(E), ctypes.byref(q), ctypes.byref(ms)))
+        return int(E.value), int(q.value), float(ms.value)
+
     # -- profiling (event pairs around launches on the plan's stream) --
     KERNELS = {"row": L.DDM_KERNEL_ROW, "col": L.DDM_KERNEL_COL, "time": L.DDM_KERNEL_TIME,
                "radial": L.DDM_KERNEL_RADIAL}
@@ -176,9 +186,15 @@ class Plan:
             out = torch.empty((self.n_q, self.max_lag), dtype=torch.float32, device=frames.device)
         _require(out, "D", (torch.float32,), (self.n_q, self.max_lag), self.device)
         with torch.cuda.device(self.device):
-            _check(_lib.ddm_structure_function(self._h, ctypes.c_void_p(frames.data_ptr()),
-                                               ctypes.c_void_p(out.data_ptr())))
+            self.last_status = _check(_lib.ddm_structure_function(self._h, ctypes.c_void_p(frames.data_ptr()),
+                                                                  ctypes.c_void_p(out.data_ptr())))
         return out
+
+    def fp16_saturations(self):
+        """Spectrum components clipped by the FP16 store since plan creation (syncs)."""
+        c = ctypes.c_int64()
+        _check(_lib.ddm_plan_fp16_saturations(self._h, ctypes.byref(c)))
+        return int(c.value)
 
     def image_spectra(self, frames, out=None):
         """F [n_q, N] complex64: step one only (frame 0 subtracted if the plan preconditions)."""
@@ -288,14 +304,12 @@ def log_bin_thresholds(n_bins, k_min, k_max):
     """n_bins logarithmic |k| bins with edges geomspace(k_min, k_max, n_bins+1).
 
     Each edge e becomes the integer threshold ceil(e^2) on k2 (so that
-    k2 >= T <=> |k| >= e for integer k2, with e^2 evaluated in FP64); repeated
-    thresholds are not allowed, so the low edges must be far enough apart.
+    k2 >= T <=> |k| >= e for integer k2, with e^2 evaluated in FP64); where low
+    edges are closer than one lattice step, equal thresholds give empty bins.
     """
     e = np.geomspace(float(k_min), float(k_max), int(n_bins) + 1)
     t = np.ceil(e * e).astype(np.int64)
     t[-1] = max(t[-1], int(np.floor(k_max * k_max)) + 1)
-    if np.any(np.diff(t) <= 0):
-        raise ValueError("log bins collapse at low k; raise k_min or lower n_bins")
     return t
 
 
@@ -380,3 +394,90 @@ class Mlp:
         _require(t, "t", (torch.float32,), (B, L.DDM_MLP_OUT), self.device)
         with torch.cuda.device(self.device):
             _check(_lib.ddm_mlp_train_step(self._h, _ptr(x), _ptr(t), B, float(lr), _ptr(self.loss_dev)))
+
+
+class Batch:
+    """Independent stacks of uneven sizes in one graph launch (ddm_batch_* of include/ddm.h).
+
+    shapes: list of (W, H, N) or dicts with Plan keyword fields (width, height,
+    n_frames, max_lag, pixel, precondition, k2_max)."""
+
+    def __init__(self, shapes, lanes=4, stream=None, device=None):
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        descs = (L.PlanDesc * len(shapes))()
+        self.shapes = []
+        for i, sh in enumerate(shapes):
+            if not isinstance(sh, dict):
+                sh = {"width": sh[0], "height": sh[1], "n_frames": sh[2]}
+            d = descs[i]
+            _lib.ddm_plan_desc_init(ctypes.byref(d))
+            d.width, d.height, d.n_frames = int(sh["width"]), int(sh["height"]), int(sh["n_frames"])
+            d.max_lag = int(sh.get("max_lag", 0))
+            pix = sh.get("pixel", "u16")
+            d.pixel = _PIX[pix] if isinstance(pix, str) else int(pix)
+            d.precondition = 1 if sh.get("precondition", True) else 0
+            d.k2_max = int(sh.get("k2_max", -1))
+            self.shapes.append(sh)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.ddm_batch_create(descs, len(shapes), int(lanes), _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self._descs = descs
+        self.n_q, self.max_lag, self.lane = [], [], []
+        for i in range(len(shapes)):
+            nq, ml, ln = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+            _check(_lib.ddm_batch_query(h, i, ctypes.byref(nq), ctypes.byref(ml), ctypes.byref(ln)))
+            self.n_q.append(int(nq.value))
+            self.max_lag.append(int(ml.value))
+            self.lane.append(int(ln.value))
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            with torch.cuda.device(self.device):
+                _check(_lib.ddm_batch_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_size(self):
+        b = ctypes.c_size_t()
+        _check(_lib.ddm_batch_workspace_size(self._h, ctypes.byref(b)))
+        return int(b.value)
+
+    def allocate_workspace(self):
+        ws = torch.empty(self.workspace_size(), dtype=torch.uint8, device="cuda:%d" % self.device)
+        _check(_lib.ddm_batch_set_workspace(self._h, ctypes.c_void_p(ws.data_ptr()), ws.numel()))
+        self._ws = ws
+        return ws
+
+    def autotune(self):
+        if self._ws is None:
+            self.allocate_workspace()
+        with torch.cuda.device(self.device):
+            _check(_lib.ddm_batch_autotune(self._h))
+
+    def structure_function(self, frames, outs=None):
+        """frames: list of [N, H, W] device tensors -> list of D [n_q, M] float32."""
+        n = len(self._descs)
+        assert len(frames) == n
+        if self._ws is None:
+            self.allocate_workspace()
+        if outs is None:
+            outs = [torch.empty((self.n_q[i], self.max_lag[i]), dtype=torch.float32, device=frames[i].device)
+                    for i in range(n)]
+        for i in range(n):
+            d = self._descs[i]
+            _require(frames[i], "frames[%d]" % i, _PIX_DTYPES[d.pixel], (d.n_frames, d.height, d.width), self.device)
+            _require(outs[i], "D[%d]" % i, (torch.float32,), (self.n_q[i], self.max_lag[i]), self.device)
+        fp = (ctypes.c_void_p * n)(*[f.data_ptr() for f in frames])
+        dp = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        with torch.cuda.device(self.device):
+            _check(_lib.ddm_batch_structure_function(self._h, fp, dp))
+        return outs

@@ -11,6 +11,9 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "internal.hpp"
@@ -82,6 +85,14 @@ struct ddm_plan_s {
   // workspace
   void* ws;
   size_t ws_bytes;
+  TimeShape tshape;  // time-kernel launch shape (autotuned or built-in)
+  // FP16 spectrum store
+  bool f16;
+  std::vector<int> pilot;  // pilot frames that fix the per-q scale
+  int32_t* sat_host;       // pinned: saturation count of the last call
+  hipEvent_t sat_ev;
+  bool sat_pending;
+  int64_t sat_total;
   // profiling: event pairs around launches of the kinds in prof_mask
   uint32_t prof_mask;
   struct Rec { uint32_t kind; hipEvent_t a, b; };
@@ -197,8 +208,6 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
     return fail(DDM_ERR_INVALID_ARGUMENT, "pixel must be DDM_PIX_U8 or DDM_PIX_U16");
   if (desc->spectrum != DDM_SPEC_F32 && desc->spectrum != DDM_SPEC_F16_QSCALED)
     return fail(DDM_ERR_INVALID_ARGUMENT, "unknown spectrum storage %d", desc->spectrum);
-  if (desc->spectrum == DDM_SPEC_F16_QSCALED)
-    return fail(DDM_ERR_UNSUPPORTED, "FP16 spectrum store is not available in this build");
   if (desc->precondition != 0 && desc->precondition != 1)
     return fail(DDM_ERR_INVALID_ARGUMENT, "precondition must be 0 or 1");
   if (desc->k2_max < -1) return fail(DDM_ERR_INVALID_ARGUMENT, "k2_max must be >= -1");
@@ -285,6 +294,25 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
     p->prof_ms[i] = 0.0;
     p->prof_n[i] = 0;
   }
+  p->f16 = desc->spectrum == DDM_SPEC_F16_QSCALED;
+  for (int j = 1; j <= 7; ++j) p->pilot.push_back((int)((int64_t)j * N / 8));
+  p->pilot.push_back(N - 1);
+  std::sort(p->pilot.begin(), p->pilot.end());
+  p->pilot.erase(std::unique(p->pilot.begin(), p->pilot.end()), p->pilot.end());
+  p->sat_host = nullptr;
+  p->sat_ev = nullptr;
+  p->sat_pending = false;
+  p->sat_total = 0;
+  if (p->f16) {
+    if ((e = hipHostMalloc((void**)&p->sat_host, sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&p->sat_ev, hipEventDisableTiming)) != hipSuccess) {
+      if (p->sat_host) hipHostFree(p->sat_host);
+      hipFree(p->dev_tables);
+      delete p;
+      return hip_fail(e, "FP16 counter setup");
+    }
+    *p->sat_host = 0;
+  }
   *out = p;
   g_err.clear();
   return DDM_OK;
@@ -295,6 +323,8 @@ ddm_status ddm_plan_destroy(ddm_plan_t p) {
   if (p->magic != kPlanMagic) return fail(DDM_ERR_STATE, "plan handle is not a live plan");
   hipStreamSynchronize(p->stream);
   prof_drain(p);
+  if (p->sat_ev) hipEventDestroy(p->sat_ev);
+  if (p->sat_host) hipHostFree(p->sat_host);
   p->magic = 0;
   if (p->dev_tables) hipFree(p->dev_tables);
   if (p->thr_d) hipFree(p->thr_d);
@@ -326,16 +356,22 @@ ddm_status ddm_plan_q_index(ddm_plan_t p, int32_t* kx_host, int32_t* ky_signed_h
   return DDM_OK;
 }
 
-static size_t spec_block_bytes(const ddm_plan_s* p) { return (size_t)p->N * kSpecQB * sizeof(float2); }
+static size_t spec_elem_bytes(const ddm_plan_s* p) { return p->f16 ? 4 : sizeof(float2); }
+static size_t spec_block_bytes(const ddm_plan_s* p) { return (size_t)p->N * kSpecQB * spec_elem_bytes(p); }
 static int64_t n_spec_blocks(const ddm_plan_s* p) { return (p->nq + kSpecQB - 1) / kSpecQB; }
+// FP16 store only: pilot spectra [nq][np], per-q exponents, saturation counter
+static size_t aux_bytes(const ddm_plan_s* p) {
+  if (!p->f16) return 0;
+  return align256((size_t)p->nq * p->pilot.size() * sizeof(float2)) + align256((size_t)p->nq * 4) + 256;
+}
 
 ddm_status ddm_plan_workspace_size(ddm_plan_t p, size_t* min_bytes, size_t* full_bytes) {
   ddm_status st = check_plan(p);
   if (st != DDM_OK) return st;
   const size_t fib = align256(p->frame_inter_bytes);
-  if (full_bytes) *full_bytes = align256((size_t)p->fb_target * p->frame_inter_bytes) +
+  if (full_bytes) *full_bytes = aux_bytes(p) + align256((size_t)p->fb_target * p->frame_inter_bytes) +
                                 (size_t)n_spec_blocks(p) * spec_block_bytes(p);
-  if (min_bytes) *min_bytes = fib + spec_block_bytes(p);
+  if (min_bytes) *min_bytes = aux_bytes(p) + fib + spec_block_bytes(p);
   return DDM_OK;
 }
 
@@ -352,26 +388,27 @@ ddm_status ddm_plan_set_workspace(ddm_plan_t p, void* ws, size_t bytes) {
   return DDM_OK;
 }
 
-// Split the workspace into the row intermediate (fb frames) and the spectra
-// store of one group (gblocks q-blocks).
+// Split the workspace (after the FP16 auxiliaries) into the row intermediate
+// (fb frames) and the spectra store of one group (gblocks q-blocks).
 static void partition(const ddm_plan_s* p, int* fb, int64_t* gblocks) {
   const size_t blk = spec_block_bytes(p);
   const int64_t nb = n_spec_blocks(p);
   const size_t fib = p->frame_inter_bytes;
   const size_t all_spec = (size_t)nb * blk;
+  const size_t room_all = p->ws_bytes - aux_bytes(p);
   int f;
   int64_t g;
-  if (p->ws_bytes >= all_spec + align256(fib)) {
+  if (room_all >= all_spec + align256(fib)) {
     g = nb;
-    size_t room = p->ws_bytes - all_spec;
+    size_t room = room_all - all_spec;
     f = (int)std::min<size_t>(p->fb_target, std::max<size_t>(1, room / fib));
     while (f > 1 && align256((size_t)f * fib) > room) --f;
   } else {
-    f = (int)std::min<size_t>(p->fb_target, std::max<size_t>(1, (p->ws_bytes / 8) / fib));
-    g = (int64_t)((p->ws_bytes - align256((size_t)f * fib)) / blk);
+    f = (int)std::min<size_t>(p->fb_target, std::max<size_t>(1, (room_all / 8) / fib));
+    g = (int64_t)((room_all - align256((size_t)f * fib)) / blk);
     if (g < 1) {
       f = 1;
-      g = (int64_t)((p->ws_bytes - align256(fib)) / blk);
+      g = (int64_t)((room_all - align256(fib)) / blk);
     }
   }
   *fb = f;
@@ -380,7 +417,7 @@ static void partition(const ddm_plan_s* p, int* fb, int64_t* gblocks) {
 
 // Step one for frames [0, N) into the spectra of q in [q_lo, q_hi).
 static ddm_status run_step_one(ddm_plan_s* p, const void* frames, float2* inter, int fb, int64_t q_lo,
-                               int64_t q_hi, int qb, float2* spec) {
+                               int64_t q_hi, int qb, SpecOut out) {
   QTable qt{p->qoff_d, p->kxcnt_d};
   for (int t0 = 0; t0 < p->N; t0 += fb) {
     const int nf = std::min(fb, p->N - t0);
@@ -388,17 +425,47 @@ static ddm_status run_step_one(ddm_plan_s* p, const void* frames, float2* inter,
     {
       ProfScope ps(p, DDM_KERNEL_ROW);
       e = launch_row(p->stream, p->d.pixel, frames, p->W, p->H, t0, nf, p->d.precondition,
-                              inter, p->kxw, p->twW, 1);
+                     inter, p->kxw, p->twW, 1);
     }
     if (e != hipSuccess) return hip_fail(e, "row transform launch");
     {
       ProfScope ps(p, DDM_KERNEL_COL);
       e = launch_col(p->stream, inter, p->H, p->kxw, p->ncol_tiles, t0, nf, p->N, qt, q_lo, q_hi, qb,
-                     spec, p->twH, 1);
+                     out, p->twH, 1);
     }
     if (e != hipSuccess) return hip_fail(e, "column transform launch");
   }
   return DDM_OK;
+}
+
+// FP16 store: transform the pilot frames (FP32, [nq][np]) and derive the per-q
+// exponents; clear the saturation counter.
+static ddm_status run_pilot(ddm_plan_s* p, const void* frames, float2* inter, float2* pilot, int32_t* qexp,
+                            int32_t* sat) {
+  QTable qt{p->qoff_d, p->kxcnt_d};
+  const int np = (int)p->pilot.size();
+  for (int i = 0; i < np; ++i) {
+    hipError_t e = launch_row(p->stream, p->d.pixel, frames, p->W, p->H, p->pilot[i], 1, p->d.precondition,
+                              inter, p->kxw, p->twW, 1);
+    if (e == hipSuccess)
+      e = launch_col(p->stream, inter, p->H, p->kxw, p->ncol_tiles, i, 1, np, qt, 0, p->nq, 1,
+                     SpecOut{pilot, nullptr, nullptr}, p->twH, 1);
+    if (e != hipSuccess) return hip_fail(e, "pilot transform launch");
+  }
+  hipError_t e = launch_qexp(p->stream, pilot, np, p->nq, qexp);
+  if (e == hipSuccess) e = launch_fill_i32(p->stream, sat, 1, 0);
+  if (e != hipSuccess) return hip_fail(e, "FP16 scale launch");
+  return DDM_OK;
+}
+
+// Fold a finished saturation count into the plan's sticky total.
+static hipError_t sat_collect(ddm_plan_s* p) {
+  if (!p->sat_pending) return hipSuccess;
+  hipError_t e = hipEventSynchronize(p->sat_ev);
+  if (e != hipSuccess) return e;
+  p->sat_total += *p->sat_host;
+  p->sat_pending = false;
+  return hipSuccess;
 }
 
 ddm_status ddm_structure_function(ddm_plan_t p, const void* frames, float* D) {
@@ -407,24 +474,54 @@ ddm_status ddm_structure_function(ddm_plan_t p, const void* frames, float* D) {
   if (frames == nullptr || D == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "frames/D is NULL");
   if (((uintptr_t)frames & 15) != 0) return fail(DDM_ERR_INVALID_ARGUMENT, "frames must be 16-byte aligned");
   if (p->ws == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "no workspace attached (ddm_plan_set_workspace)");
+  hipError_t e = sat_collect(p);
+  if (e != hipSuccess) return hip_fail(e, "saturation count");
   int fb;
   int64_t gblocks;
   partition(p, &fb, &gblocks);
-  float2* inter = (float2*)p->ws;
-  float2* spec = (float2*)((char*)p->ws + align256((size_t)fb * p->frame_inter_bytes));
+  char* base = (char*)p->ws;
+  float2* pilot = nullptr;
+  int32_t *qexp = nullptr, *sat = nullptr;
+  if (p->f16) {
+    pilot = (float2*)base;
+    qexp = (int32_t*)(base + align256((size_t)p->nq * p->pilot.size() * sizeof(float2)));
+    sat = (int32_t*)((char*)qexp + align256((size_t)p->nq * 4));
+    base += aux_bytes(p);
+  }
+  float2* inter = (float2*)base;
+  void* spec = base + align256((size_t)fb * p->frame_inter_bytes);
+  if (p->f16) {
+    st = run_pilot(p, frames, inter, pilot, qexp, sat);
+    if (st != DDM_OK) return st;
+  }
   const int64_t gq = gblocks * kSpecQB;
   for (int64_t q_lo = 0; q_lo < p->nq; q_lo += gq) {
     const int64_t q_hi = std::min(p->nq, q_lo + gq);
-    st = run_step_one(p, frames, inter, fb, q_lo, q_hi, kSpecQB, spec);
+    st = run_step_one(p, frames, inter, fb, q_lo, q_hi, kSpecQB, SpecOut{spec, qexp, sat});
     if (st != DDM_OK) return st;
-    hipError_t e;
     {
       ProfScope ps(p, DDM_KERNEL_TIME);
       e = launch_time(p->stream, spec, kSpecQB, q_hi - q_lo, p->N, p->M, p->twT, p->ramp,
-                      D + (size_t)q_lo * p->M);
+                      qexp ? qexp + q_lo : nullptr, D + (size_t)q_lo * p->M, p->tshape);
     }
     if (e != hipSuccess) return hip_fail(e, "time transform launch");
   }
+  if (p->f16) {
+    e = hipMemcpyAsync(p->sat_host, sat, sizeof(int32_t), hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipEventRecord(p->sat_ev, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "saturation count copy");
+    p->sat_pending = true;
+  }
+  return p->sat_total > 0 ? DDM_WARN_FP16_SATURATED : DDM_OK;
+}
+
+ddm_status ddm_plan_fp16_saturations(ddm_plan_t p, int64_t* count) {
+  ddm_status st = check_plan(p);
+  if (st != DDM_OK) return st;
+  if (count == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "count is NULL");
+  hipError_t e = sat_collect(p);
+  if (e != hipSuccess) return hip_fail(e, "saturation count");
+  *count = p->sat_total;
   return DDM_OK;
 }
 
@@ -438,7 +535,7 @@ ddm_status ddm_image_spectra(ddm_plan_t p, const void* frames, float* spectra) {
   const size_t fib = p->frame_inter_bytes;
   int fb = (int)std::min<size_t>(p->fb_target, std::max<size_t>(1, p->ws_bytes / fib));
   while (fb > 1 && (size_t)fb * fib > p->ws_bytes) --fb;
-  return run_step_one(p, frames, (float2*)p->ws, fb, 0, p->nq, 1, (float2*)spectra);
+  return run_step_one(p, frames, (float2*)p->ws, fb, 0, p->nq, 1, SpecOut{spectra, nullptr, nullptr});
 }
 
 ddm_status ddm_structure_from_spectra(ddm_plan_t p, const float* spectra, float* D) {
@@ -448,7 +545,7 @@ ddm_status ddm_structure_from_spectra(ddm_plan_t p, const float* spectra, float*
   hipError_t e;
   {
     ProfScope ps(p, DDM_KERNEL_TIME);
-    e = launch_time(p->stream, (const float2*)spectra, 1, p->nq, p->N, p->M, p->twT, p->ramp, D);
+    e = launch_time(p->stream, spectra, 1, p->nq, p->N, p->M, p->twT, p->ramp, nullptr, D, p->tshape);
   }
   if (e != hipSuccess) return hip_fail(e, "time transform launch");
   return DDM_OK;
@@ -464,8 +561,8 @@ ddm_status ddm_radial_average(ddm_plan_t p, const float* D, const int64_t* thr, 
     return fail(DDM_ERR_INVALID_ARGUMENT, "Dbar/counts is NULL");
   if (thr[0] < 0) return fail(DDM_ERR_INVALID_ARGUMENT, "thresholds must be >= 0");
   for (int b = 0; b < n_bins; ++b)
-    if (thr[b + 1] <= thr[b])
-      return fail(DDM_ERR_INVALID_ARGUMENT, "thresholds must be strictly increasing (at %d)", b);
+    if (thr[b + 1] < thr[b])
+      return fail(DDM_ERR_INVALID_ARGUMENT, "thresholds must be non-decreasing (at %d)", b);
   const size_t need = (size_t)(n_bins + 1) * sizeof(int64_t);
   if (need > p->thr_cap) {
     hipError_t e = hipStreamSynchronize(p->stream);  // the old buffer may still be read
@@ -583,6 +680,352 @@ ddm_status ddm_fit(const ddm_fit_desc* f, const float* curves, const float* lags
   hipError_t e = launch_lm(s, curves, n, ls, init, prm, nullptr, params, iters, flags);
   if (e == hipSuccess && fb) e = launch_lm(s, curves, n, ls, nullptr, prm, flags, params, iters, flags);
   if (e != hipSuccess) return hip_fail(e, "fit launch");
+  return DDM_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Autotuner of the time-kernel launch shape.  Candidates (E in {16, 8} x wave
+// vectors per workgroup in {1, 2, 4, 8, 16}, those that fit) are timed with
+// HIP events on zero-filled spectra in the plan's workspace; the fastest is
+// kept per (L, N, M, storage) for the process.  DDM_AUTOTUNE=off keeps the
+// built-in choice.
+// ---------------------------------------------------------------------------
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int, int>, std::tuple<int, int, double>> g_tune;
+
+ddm_status ddm_plan_autotune(ddm_plan_t p, int32_t* E_out, int32_t* qpw_out, double* ms_out) {
+  ddm_status st = check_plan(p);
+  if (st != DDM_OK) return st;
+  if (p->ws == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "autotune needs the workspace (ddm_plan_set_workspace)");
+  const char* env = std::getenv("DDM_AUTOTUNE");
+  const auto key = std::make_tuple(p->L, p->N, p->M, (int)p->f16);
+  double best_ms = -1.0;
+  TimeShape best{};
+  bool have = false;
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      best.E = std::get<0>(it->second);
+      best.qpw = std::get<1>(it->second);
+      best_ms = std::get<2>(it->second);
+      have = true;
+    }
+  }
+  if (!have && !(env && std::strcmp(env, "off") == 0)) {
+    int fb;
+    int64_t gblocks;
+    partition(p, &fb, &gblocks);
+    char* base = (char*)p->ws + aux_bytes(p);
+    float* dout = (float*)base;                       // row-intermediate region as D scratch
+    void* spec = base + align256((size_t)fb * p->frame_inter_bytes);
+    int64_t nq_t = std::min<int64_t>(gblocks * kSpecQB, 65536);
+    nq_t = std::min<int64_t>(nq_t, (int64_t)(((size_t)fb * p->frame_inter_bytes) / ((size_t)p->M * 4)));
+    nq_t = std::min<int64_t>(nq_t, p->nq);
+    if (nq_t < 1) return fail(DDM_ERR_OUT_OF_MEMORY, "workspace too small to autotune");
+    const int64_t words = ((size_t)((nq_t + kSpecQB - 1) / kSpecQB) * spec_block_bytes(p)) / 4;
+    hipError_t e = launch_fill_i32(p->stream, (int32_t*)spec, words, 0);
+    int32_t* qexp = nullptr;
+    if (p->f16 && e == hipSuccess) {
+      qexp = (int32_t*)((char*)p->ws + align256((size_t)p->nq * p->pilot.size() * sizeof(float2)));
+      e = launch_fill_i32(p->stream, qexp, nq_t, 0);
+    }
+    hipEvent_t a = nullptr, b = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    for (int E : {16, 8}) {
+      for (int qpw : {1, 2, 4, 8, 16}) {
+        if (e != hipSuccess) break;
+        if (p->L / E < 1 || p->L % E != 0 || (E == 8 && p->L < 512)) continue;
+        if (qpw * (p->L / E) > 1024 || (size_t)qpw * (2 * p->L + p->L / 8 + 1) * 8 > 160 * 1024) continue;
+        const TimeShape sh{E, qpw};
+        e = launch_time(p->stream, spec, kSpecQB, nq_t, p->N, p->M, p->twT, p->ramp, qexp, dout, sh);
+        if (e == hipSuccess) e = hipEventRecord(a, p->stream);
+        for (int r = 0; r < 2 && e == hipSuccess; ++r)
+          e = launch_time(p->stream, spec, kSpecQB, nq_t, p->N, p->M, p->twT, p->ramp, qexp, dout, sh);
+        if (e == hipSuccess) e = hipEventRecord(b, p->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e == hipSuccess && (best_ms < 0 || ms < best_ms)) {
+          best_ms = ms;
+          best = sh;
+        }
+      }
+    }
+    if (a) hipEventDestroy(a);
+    if (b) hipEventDestroy(b);
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    best_ms = best_ms / 2.0 * ((double)p->nq / (double)nq_t);  // per launch over all q
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[key] = std::make_tuple(best.E, best.qpw, best_ms);
+  }
+  p->tshape = best;
+  if (E_out) *E_out = best.E;
+  if (qpw_out) *qpw_out = best.qpw;
+  if (ms_out) *ms_out = best_ms;
+  return DDM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches of independent stacks of uneven sizes.  Each stack has its own plan;
+// stacks are spread over `lanes` streams (largest first onto the least loaded
+// lane); each lane owns one slice of the workspace, reused by its stacks in
+// turn.  The whole fork / join sequence is captured once into a HIP graph and
+// replayed with one hipGraphLaunch per call.
+// ---------------------------------------------------------------------------
+struct ddm_batch_s {
+  uint32_t magic;
+  hipStream_t stream;  // caller's stream
+  hipStream_t root;    // internal stream the graph is captured on and launched on
+  hipEvent_t in_ev, out_ev;
+  std::vector<ddm_plan_t> plans;
+  std::vector<int> lane_of;
+  std::vector<hipStream_t> lanes;
+  std::vector<size_t> lane_bytes, lane_off;
+  hipEvent_t fork;
+  std::vector<hipEvent_t> join;
+  hipGraphExec_t exec;
+  std::vector<const void*> g_frames;
+  std::vector<float*> g_D;
+  void* ws;
+  size_t ws_bytes;
+};
+static constexpr uint32_t kBatchMagic = 0x44444d42u;
+
+static ddm_status check_batch(ddm_batch_t b) {
+  if (b == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "batch is NULL");
+  if (b->magic != kBatchMagic) return fail(DDM_ERR_STATE, "batch handle is not live");
+  return DDM_OK;
+}
+
+static void batch_free(ddm_batch_s* b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->root) hipStreamDestroy(b->root);
+  if (b->in_ev) hipEventDestroy(b->in_ev);
+  if (b->out_ev) hipEventDestroy(b->out_ev);
+  for (auto* p : b->plans) ddm_plan_destroy(p);
+  for (auto s : b->lanes) hipStreamDestroy(s);
+  if (b->fork) hipEventDestroy(b->fork);
+  for (auto e : b->join) hipEventDestroy(e);
+  b->magic = 0;
+  delete b;
+}
+
+ddm_status ddm_batch_create(const ddm_plan_desc* descs, int32_t n, int32_t lanes, void* stream, ddm_batch_t* out) {
+  if (out == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (descs == nullptr || n < 1) return fail(DDM_ERR_INVALID_ARGUMENT, "need at least one descriptor");
+  if (lanes < 1 || lanes > 16) return fail(DDM_ERR_INVALID_ARGUMENT, "lanes must be in [1, 16]");
+  for (int i = 0; i < n; ++i)
+    if (descs[i].spectrum != DDM_SPEC_F32)
+      return fail(DDM_ERR_UNSUPPORTED, "batched stacks use FP32 spectra (stack %d)", i);
+  ddm_batch_s* b = new (std::nothrow) ddm_batch_s();
+  if (b == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  b->magic = kBatchMagic;
+  b->stream = (hipStream_t)stream;
+  b->fork = nullptr;
+  b->exec = nullptr;
+  b->ws = nullptr;
+  b->ws_bytes = 0;
+  b->root = nullptr;
+  b->in_ev = b->out_ev = nullptr;
+  {
+    hipError_t e0 = hipStreamCreateWithFlags(&b->root, hipStreamNonBlocking);
+    if (e0 == hipSuccess) e0 = hipEventCreateWithFlags(&b->in_ev, hipEventDisableTiming);
+    if (e0 == hipSuccess) e0 = hipEventCreateWithFlags(&b->out_ev, hipEventDisableTiming);
+    if (e0 != hipSuccess) {
+      batch_free(b);
+      return hip_fail(e0, "batch stream setup");
+    }
+  }
+  lanes = std::min(lanes, n);
+  for (int l = 0; l < lanes; ++l) {
+    hipStream_t s;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      batch_free(b);
+      return hip_fail(e, "hipStreamCreate");
+    }
+    b->lanes.push_back(s);
+    hipEvent_t ev;
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) {
+      batch_free(b);
+      return hip_fail(e, "hipEventCreate");
+    }
+    b->join.push_back(ev);
+  }
+  hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    batch_free(b);
+    return hip_fail(e, "hipEventCreate");
+  }
+  // plans, then lanes: largest stacks first onto the least loaded lane
+  std::vector<size_t> full(n);
+  std::vector<double> work(n);
+  for (int i = 0; i < n; ++i) {
+    ddm_plan_desc d = descs[i];
+    ddm_plan_t p = nullptr;
+    ddm_status st = ddm_plan_create(&d, &p);
+    if (st != DDM_OK) {
+      std::string msg = g_err;
+      batch_free(b);
+      return fail(st, "stack %d: %s", i, msg.c_str());
+    }
+    b->plans.push_back(p);
+    size_t mn;
+    ddm_plan_workspace_size(p, &mn, &full[i]);
+    work[i] = (double)d.n_frames * d.width * d.height;
+  }
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+  std::vector<double> load(lanes, 0.0);
+  b->lane_of.assign(n, 0);
+  b->lane_bytes.assign(lanes, 0);
+  for (int i : order) {
+    int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    b->lane_of[i] = l;
+    load[l] += work[i];
+    b->lane_bytes[l] = std::max(b->lane_bytes[l], align256(full[i]));
+    b->plans[i]->stream = b->lanes[l];
+  }
+  size_t off = 0;
+  for (int l = 0; l < lanes; ++l) {
+    b->lane_off.push_back(off);
+    off += b->lane_bytes[l];
+  }
+  *out = b;
+  g_err.clear();
+  return DDM_OK;
+}
+
+ddm_status ddm_batch_destroy(ddm_batch_t b) {
+  if (b == nullptr) return DDM_OK;
+  ddm_status st = check_batch(b);
+  if (st != DDM_OK) return st;
+  hipStreamSynchronize(b->stream);
+  hipStreamSynchronize(b->root);
+  for (auto s : b->lanes) hipStreamSynchronize(s);
+  batch_free(b);
+  return DDM_OK;
+}
+
+ddm_status ddm_batch_query(ddm_batch_t b, int32_t stack, int64_t* n_q, int32_t* max_lag, int32_t* lane) {
+  ddm_status st = check_batch(b);
+  if (st != DDM_OK) return st;
+  if (stack < 0 || stack >= (int)b->plans.size()) return fail(DDM_ERR_INVALID_ARGUMENT, "stack out of range");
+  if (lane) *lane = b->lane_of[stack];
+  return ddm_plan_query(b->plans[stack], n_q, max_lag, nullptr);
+}
+
+ddm_status ddm_batch_workspace_size(ddm_batch_t b, size_t* bytes) {
+  ddm_status st = check_batch(b);
+  if (st != DDM_OK) return st;
+  if (bytes == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "bytes is NULL");
+  size_t t = 0;
+  for (size_t x : b->lane_bytes) t += x;
+  *bytes = t;
+  return DDM_OK;
+}
+
+ddm_status ddm_batch_set_workspace(ddm_batch_t b, void* ws, size_t bytes) {
+  ddm_status st = check_batch(b);
+  if (st != DDM_OK) return st;
+  size_t need;
+  ddm_batch_workspace_size(b, &need);
+  if (ws == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (((uintptr_t)ws & 255) != 0) return fail(DDM_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+  if (bytes < need) return fail(DDM_ERR_OUT_OF_MEMORY, "workspace %zu bytes < %zu", bytes, need);
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    const int l = b->lane_of[i];
+    st = ddm_plan_set_workspace(b->plans[i], (char*)ws + b->lane_off[l], b->lane_bytes[l]);
+    if (st != DDM_OK) return st;
+  }
+  b->ws = ws;
+  b->ws_bytes = bytes;
+  if (b->exec) {  // the captured graph refers to the old workspace
+    hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  return DDM_OK;
+}
+
+ddm_status ddm_batch_autotune(ddm_batch_t b) {
+  ddm_status st = check_batch(b);
+  if (st != DDM_OK) return st;
+  if (b->ws == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "no workspace attached");
+  for (auto* p : b->plans) {
+    st = ddm_plan_autotune(p, nullptr, nullptr, nullptr);
+    if (st != DDM_OK) return st;
+  }
+  if (b->exec) {
+    hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  return DDM_OK;
+}
+
+static ddm_status batch_enqueue(ddm_batch_s* b, const void* const* frames, float* const* D) {
+  hipError_t e = hipEventRecord(b->fork, b->root);
+  for (size_t l = 0; l < b->lanes.size() && e == hipSuccess; ++l) e = hipStreamWaitEvent(b->lanes[l], b->fork, 0);
+  if (e != hipSuccess) return hip_fail(e, "batch fork");
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    ddm_status st = ddm_structure_function(b->plans[i], frames[i], D[i]);
+    if (st != DDM_OK) return st;
+  }
+  for (size_t l = 0; l < b->lanes.size() && e == hipSuccess; ++l) {
+    e = hipEventRecord(b->join[l], b->lanes[l]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->root, b->join[l], 0);
+  }
+  if (e != hipSuccess) return hip_fail(e, "batch join");
+  return DDM_OK;
+}
+
+ddm_status ddm_batch_structure_function(ddm_batch_t b, const void* const* frames, float* const* D) {
+  ddm_status st = check_batch(b);
+  if (st != DDM_OK) return st;
+  if (frames == nullptr || D == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "pointer arrays are NULL");
+  if (b->ws == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "no workspace attached");
+  const size_t n = b->plans.size();
+  for (size_t i = 0; i < n; ++i) {
+    if (frames[i] == nullptr || D[i] == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "stack %zu: NULL pointer", i);
+    if (((uintptr_t)frames[i] & 15) != 0) return fail(DDM_ERR_INVALID_ARGUMENT, "stack %zu: frames not 16-byte aligned", i);
+  }
+  bool same = b->exec != nullptr && b->g_frames.size() == n;
+  for (size_t i = 0; same && i < n; ++i) same = b->g_frames[i] == frames[i] && b->g_D[i] == D[i];
+  if (!same) {
+    if (b->exec) {
+      hipGraphExecDestroy(b->exec);
+      b->exec = nullptr;
+    }
+    hipError_t e = hipStreamBeginCapture(b->root, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    st = batch_enqueue(b, frames, D);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->root, &g);
+    if (st != DDM_OK) {
+      if (g) hipGraphDestroy(g);
+      return st;
+    }
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      b->exec = nullptr;
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    b->g_frames.assign(frames, frames + n);
+    b->g_D.assign(D, D + n);
+  }
+  // order after the caller's stream, launch, and order the caller's stream after it
+  hipError_t e = hipEventRecord(b->in_ev, b->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(b->root, b->in_ev, 0);
+  if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->root);
+  if (e == hipSuccess) e = hipEventRecord(b->out_ev, b->root);
+  if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->out_ev, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   return DDM_OK;
 }
 

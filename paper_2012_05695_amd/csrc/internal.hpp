@@ -73,12 +73,33 @@ hipError_t launch_row(hipStream_t s, int pixel, const void* frames, int W, int H
                       int nframes, int precondition, float2* inter, int kxw,
                       const float2* tw, int tws);
 
+// Destination of the column transform: complex FP32, or complex FP16 scaled
+// by 2^qexp[q] when qexp is non-null (saturations counted in *sat).
+struct SpecOut {
+  void* spec;
+  const int32_t* qexp;
+  int32_t* sat;
+};
+
 hipError_t launch_col(hipStream_t s, const float2* inter, int H, int kxw, int ntiles,
                       int64_t t0, int nframes, int N, QTable qt, int64_t q_lo, int64_t q_hi,
-                      int qb, float2* spec, const float2* tw, int tws);
+                      int qb, SpecOut out, const float2* tw, int tws);
 
-hipError_t launch_time(hipStream_t s, const float2* spec, int qb, int64_t nq_group, int N, int M,
-                       const float2* twN2, const double* ramp, float* D_rows);
+hipError_t launch_qexp(hipStream_t s, const float2* pilot, int np, int64_t nq, int32_t* qexp);
+hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
+
+// spec: complex FP32, or complex FP16 scaled by 2^qexp[q] when qexp is non-null
+// (qexp indexed by the group-local q).
+// Launch shape of the time kernel: values per thread E (8 or 16) and wave
+// vectors per workgroup; 0 picks the built-in choice for the length.
+struct TimeShape {
+  int E = 0;
+  int qpw = 0;
+};
+
+hipError_t launch_time(hipStream_t s, const void* spec, int qb, int64_t nq_group, int N, int M,
+                       const float2* twN2, const double* ramp, const int32_t* qexp, float* D_rows,
+                       TimeShape shape = TimeShape{});
 
 hipError_t launch_radial(hipStream_t s, const float* D, int64_t nq, int M, int W, int H,
                          int64_t ca, int64_t cc, QTable qt, const int64_t* thr, int nbins,

@@ -11,6 +11,8 @@
 //   k_col: complex FFT of length H down each kx column, then a direct write of
 //          the kept wave vectors into the q-blocked spectra store
 //          [block][t][QB] (the transpose to time series is this write).
+#include <hip/hip_fp16.h>
+
 #include "fft.hpp"
 #include "internal.hpp"
 
@@ -96,11 +98,14 @@ __global__ void __launch_bounds__(256) k_row(const PIX* __restrict__ frames, int
   }
 }
 
-template <int H, int E, int CW>
+// F16: store complex FP16 scaled by 2^qexp[q] (round to nearest even),
+// clamping |value| > 65504 and counting each clamped component in *sat.
+template <int H, int E, int CW, bool F16>
 __global__ void __launch_bounds__(1024) k_col(const float2* __restrict__ inter, int kxw, int64_t t0,
                                               int N, const int32_t* __restrict__ qoff,
                                               const int32_t* __restrict__ kxcnt, int64_t q_lo,
-                                              int64_t q_hi, int qb, float2* __restrict__ spec,
+                                              int64_t q_hi, int qb, void* __restrict__ spec,
+                                              const int32_t* __restrict__ qexp, int32_t* sat,
                                               const float2* __restrict__ tw, int tws) {
   constexpr int T = H / E;
   extern __shared__ float2 lds_col[];
@@ -114,6 +119,7 @@ __global__ void __launch_bounds__(1024) k_col(const float2* __restrict__ inter, 
   LdsView<CW> buf{lds_col + c};
   fft_forward<H, E, CW>(v, buf, tid, tw, tws);
   const int64_t t = t0 + blockIdx.y;
+  int nsat = 0;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int ky = tid + e * T;
@@ -121,10 +127,46 @@ __global__ void __launch_bounds__(1024) k_col(const float2* __restrict__ inter, 
       const int64_t q = (int64_t)qoff[ky] + kx;
       if (q >= q_lo && q < q_hi) {
         const int64_t j = q - q_lo;
-        spec[((j / qb) * N + t) * qb + (j % qb)] = v[e];
+        const size_t at = ((j / qb) * N + t) * qb + (j % qb);
+        if constexpr (F16) {
+          float re = ldexpf(v[e].x, qexp[q]), im = ldexpf(v[e].y, qexp[q]);
+          const float lim = 65504.0f;
+          if (!(fabsf(re) <= lim)) { re = copysignf(lim, re); ++nsat; }
+          if (!(fabsf(im) <= lim)) { im = copysignf(lim, im); ++nsat; }
+          reinterpret_cast<__half2*>(spec)[at] = __halves2half2(__float2half_rn(re), __float2half_rn(im));
+        } else {
+          reinterpret_cast<float2*>(spec)[at] = v[e];
+        }
       }
     }
   }
+  if (F16 && nsat > 0) atomicAdd(sat, nsat);
+}
+
+// Per-q exponent of the FP16 store: the largest |component| over the pilot
+// frames is mapped into (2^10, 2^11], leaving a factor 32 of headroom below
+// the FP16 maximum for the other frames.  pilot: [nq][np] complex FP32.
+__global__ void k_qexp(const float2* __restrict__ pilot, int np, int64_t nq, int32_t* __restrict__ qexp) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  float mx = 0.0f;
+  for (int i = 0; i < np; ++i) {
+    const float2 a = pilot[q * np + i];
+    mx = fmaxf(mx, fmaxf(fabsf(a.x), fabsf(a.y)));
+  }
+  int e = 0;
+  if (mx > 0.0f && isfinite(mx)) {
+    int ex;
+    const float m = frexpf(mx, &ex);  // mx = m 2^ex, m in [0.5, 1)
+    const int c = (m == 0.5f) ? ex - 1 : ex;  // ceil(log2 mx)
+    e = 11 - c;
+  }
+  qexp[q] = e;
+}
+
+__global__ void k_fill_i32s(int32_t* p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 bool supported_spatial(int n) {
@@ -200,21 +242,27 @@ hipError_t launch_row(hipStream_t s, int pixel, const void* frames, int W, int H
 template <int H>
 static hipError_t col_go(hipStream_t s, const float2* inter, int kxw, int ntiles, int64_t t0,
                          int nframes, int N, QTable qt, int64_t q_lo, int64_t q_hi, int qb,
-                         float2* spec, const float2* tw, int tws) {
+                         SpecOut out, const float2* tw, int tws) {
   constexpr int E = (H % 3 == 0) ? 24 : 16;
   constexpr int T = H / E;
   constexpr int CW = (16 * H * 8 <= 131072) ? 16 : (8 * H * 8 <= 131072) ? 8 : 4;
   dim3 grid(ntiles, nframes);
-  hipLaunchKernelGGL((k_col<H, E, CW>), grid, dim3(CW * T), (size_t)CW * H * sizeof(float2), s,
-                     inter, kxw, t0, N, qt.qoff, qt.kxcnt, q_lo, q_hi, qb, spec, tw, tws);
+  if (out.qexp != nullptr)
+    hipLaunchKernelGGL((k_col<H, E, CW, true>), grid, dim3(CW * T), (size_t)CW * H * sizeof(float2), s,
+                       inter, kxw, t0, N, qt.qoff, qt.kxcnt, q_lo, q_hi, qb, out.spec, out.qexp, out.sat, tw,
+                       tws);
+  else
+    hipLaunchKernelGGL((k_col<H, E, CW, false>), grid, dim3(CW * T), (size_t)CW * H * sizeof(float2), s,
+                       inter, kxw, t0, N, qt.qoff, qt.kxcnt, q_lo, q_hi, qb, out.spec, nullptr, nullptr, tw,
+                       tws);
   return hipGetLastError();
 }
 
 hipError_t launch_col(hipStream_t s, const float2* inter, int H, int kxw, int ntiles, int64_t t0,
                       int nframes, int N, QTable qt, int64_t q_lo, int64_t q_hi, int qb,
-                      float2* spec, const float2* tw, int tws) {
+                      SpecOut out, const float2* tw, int tws) {
   switch (H) {
-#define COL_CASE(n) case n: return col_go<n>(s, inter, kxw, ntiles, t0, nframes, N, qt, q_lo, q_hi, qb, spec, tw, tws);
+#define COL_CASE(n) case n: return col_go<n>(s, inter, kxw, ntiles, t0, nframes, N, qt, q_lo, q_hi, qb, out, tw, tws);
     COL_CASE(16) COL_CASE(32) COL_CASE(64) COL_CASE(128) COL_CASE(256) COL_CASE(512)
     COL_CASE(1024) COL_CASE(2048) COL_CASE(4096)
     COL_CASE(48) COL_CASE(96) COL_CASE(192) COL_CASE(384) COL_CASE(768) COL_CASE(1536) COL_CASE(3072)
@@ -222,6 +270,18 @@ hipError_t launch_col(hipStream_t s, const float2* inter, int H, int kxw, int nt
     default:
       return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_qexp(hipStream_t s, const float2* pilot, int np, int64_t nq, int32_t* qexp) {
+  if (nq == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_qexp, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, pilot, np, nq, qexp);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32s, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
 }
 
 }  // namespace ddm

@@ -35,6 +35,8 @@
 // the L-point twiddle table, read by every pass of all three transforms.  Global reads
 // use buffer loads (scalar base, 32-bit offsets; reads past the described
 // range return 0, which supplies the zero padding).
+#include <hip/hip_fp16.h>
+
 #include <cstdlib>
 
 #include "fft.hpp"
@@ -112,10 +114,13 @@ __device__ __forceinline__ double group_excl_scan(double v, int tid, double* scr
 
 // QB: layout of the input time series.  QB == 1: plain q-major [q][N].
 // QB > 1: the blocked store [q / QB][N][QB] written by the column transform.
-template <int L, int QPW, int QB, int E, bool TWL>
-__global__ void __launch_bounds__(QPW * (L / E)) k_time(const float2* __restrict__ spec, int64_t nq,
+// F16 (blocked store only): complex FP16 scaled by 2^qexp[q], unscaled on load
+// (exact: a power of two).
+template <int L, int QPW, int QB, int E, bool TWL, bool F16>
+__global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__ spec, int64_t nq,
                                                        int N, int M, const float2* __restrict__ twN2,
                                                        const double* __restrict__ ramp,
+                                                       const int32_t* __restrict__ qexp,
                                                        float* __restrict__ D) {
   constexpr int T = L / E;
   constexpr bool WAVE = (T <= 64);
@@ -155,15 +160,21 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const float2* __restrict
   // ---- cooperative load of QPW time sequences into LDS, [q][t] ----
   {
     __amdgpu_buffer_rsrc_t in_r;
+    constexpr uint32_t ES = F16 ? 4u : 8u;  // bytes per stored complex value
     if constexpr (QB == 1) {
       const int64_t nvalid = (nq - q0) < QPW ? (nq - q0) : QPW;
-      in_r = make_rsrc(spec + (size_t)q0 * N, (uint32_t)(nvalid * N * sizeof(float2)));
+      in_r = make_rsrc((const float2*)spec + (size_t)q0 * N, (uint32_t)(nvalid * N * sizeof(float2)));
     } else {
       // rows t < N of this sub-block; t >= N falls past the range and reads 0
       const int64_t blk = q0 / QB;
       const int sub = (int)(q0 % QB);
-      in_r = make_rsrc(spec + (size_t)blk * N * QB + sub,
-                       (uint32_t)(((size_t)(N - 1) * QB + QPW) * sizeof(float2)));
+      in_r = make_rsrc((const char*)spec + ((size_t)blk * N * QB + sub) * ES,
+                       (uint32_t)(((size_t)(N - 1) * QB + QPW) * ES));
+    }
+    float sc = 1.0f;  // 2^-qexp of this thread's wave vector (blocked layout: i = threadIdx.x % QPW)
+    if constexpr (F16) {
+      const int64_t qq = q0 + (threadIdx.x % QPW);
+      sc = (qq < nq) ? ldexpf(1.0f, -qexp[qq]) : 1.0f;
     }
     float2 ld[E];
 #pragma unroll
@@ -175,9 +186,15 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const float2* __restrict
         off = (t < N) ? (uint32_t)(i * N + t) * 8u : 0xFFFFFFF0u;
       } else {
         const int t = f / QPW, i = f % QPW;
-        off = (uint32_t)(t * QB + i) * 8u;
+        off = (uint32_t)(t * QB + i) * ES;
       }
-      ld[r] = ld_f2(in_r, off);
+      if constexpr (F16) {
+        const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(in_r, off, 0, 0);
+        const __half2 h = __builtin_bit_cast(__half2, w);
+        ld[r] = make_float2(__low2float(h) * sc, __high2float(h) * sc);
+      } else {
+        ld[r] = ld_f2(in_r, off);
+      }
     }
 #pragma unroll
     for (int r = 0; r < E; ++r) {
@@ -335,8 +352,8 @@ static bool time_twl() {
 }
 
 template <int L, int QPW, int QB, int E>
-static hipError_t time_go(hipStream_t s, const float2* spec, int64_t nq, int N, int M,
-                          const float2* tw, const double* ramp, float* D) {
+static hipError_t time_go(hipStream_t s, const void* spec, int64_t nq, int N, int M,
+                          const float2* tw, const double* ramp, const int32_t* qexp, float* D) {
   int64_t nwg;
   if (QPW >= QB) {
     nwg = (nq + QPW - 1) / QPW;
@@ -345,15 +362,30 @@ static hipError_t time_go(hipStream_t s, const float2* spec, int64_t nq, int N, 
     nwg = ((nblocks + 7) / 8) * 8 * (QB / QPW);
   }
   if (nwg == 0) return hipSuccess;
+  const dim3 grid((unsigned)nwg), block(QPW * (L / E));
   if constexpr (QPW * (2 * L + L / 8 + 1) * 8 + L * 8 <= 163840) {
     if (time_twl()) {
-      hipLaunchKernelGGL((k_time<L, QPW, QB, E, true>), dim3((unsigned)nwg), dim3(QPW * (L / E)), 0, s,
-                         spec, nq, N, M, tw, ramp, D);
+      if constexpr (QB > 1) {
+        if (qexp != nullptr) {
+          hipLaunchKernelGGL((k_time<L, QPW, QB, E, true, true>), grid, block, 0, s, spec, nq, N, M, tw, ramp,
+                             qexp, D);
+          return hipGetLastError();
+        }
+      }
+      hipLaunchKernelGGL((k_time<L, QPW, QB, E, true, false>), grid, block, 0, s, spec, nq, N, M, tw, ramp,
+                         nullptr, D);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_time<L, QPW, QB, E, false>), dim3((unsigned)nwg), dim3(QPW * (L / E)), 0, s, spec,
-                     nq, N, M, tw, ramp, D);
+  if constexpr (QB > 1) {
+    if (qexp != nullptr) {
+      hipLaunchKernelGGL((k_time<L, QPW, QB, E, false, true>), grid, block, 0, s, spec, nq, N, M, tw, ramp,
+                         qexp, D);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_time<L, QPW, QB, E, false, false>), grid, block, 0, s, spec, nq, N, M, tw, ramp,
+                     nullptr, D);
   return hipGetLastError();
 }
 
@@ -363,56 +395,61 @@ static constexpr bool qpw_fits() {
 }
 
 template <int L, int QB, int E>
-static hipError_t time_qpw_go(hipStream_t s, int qpw, const float2* spec, int64_t nq, int N, int M,
-                              const float2* tw, const double* ramp, float* D) {
+static hipError_t time_qpw_go(hipStream_t s, int qpw, const void* spec, int64_t nq, int N, int M,
+                              const float2* tw, const double* ramp, const int32_t* qexp, float* D) {
   switch (qpw) {
-    case 16: if constexpr (qpw_fits<L, 16, E>()) return time_go<L, 16, QB, E>(s, spec, nq, N, M, tw, ramp, D);
+    case 16: if constexpr (qpw_fits<L, 16, E>()) return time_go<L, 16, QB, E>(s, spec, nq, N, M, tw, ramp, qexp, D);
              break;
-    case 8: if constexpr (qpw_fits<L, 8, E>()) return time_go<L, 8, QB, E>(s, spec, nq, N, M, tw, ramp, D);
+    case 8: if constexpr (qpw_fits<L, 8, E>()) return time_go<L, 8, QB, E>(s, spec, nq, N, M, tw, ramp, qexp, D);
             break;
-    case 4: if constexpr (qpw_fits<L, 4, E>()) return time_go<L, 4, QB, E>(s, spec, nq, N, M, tw, ramp, D);
+    case 4: if constexpr (qpw_fits<L, 4, E>()) return time_go<L, 4, QB, E>(s, spec, nq, N, M, tw, ramp, qexp, D);
             break;
-    case 2: if constexpr (qpw_fits<L, 2, E>()) return time_go<L, 2, QB, E>(s, spec, nq, N, M, tw, ramp, D);
+    case 2: if constexpr (qpw_fits<L, 2, E>()) return time_go<L, 2, QB, E>(s, spec, nq, N, M, tw, ramp, qexp, D);
             break;
-    case 1: return time_go<L, 1, QB, E>(s, spec, nq, N, M, tw, ramp, D);
+    case 1: return time_go<L, 1, QB, E>(s, spec, nq, N, M, tw, ramp, qexp, D);
   }
   return hipErrorInvalidValue;
 }
 
 template <int L, int QB>
-static hipError_t time_e_go(hipStream_t s, const float2* spec, int64_t nq, int N, int M,
-                            const float2* tw, const double* ramp, float* D) {
-  const int E = time_e(L);
-  const int qpw = time_qpw(L, E);
+static hipError_t time_e_go(hipStream_t s, const void* spec, int64_t nq, int N, int M,
+                            const float2* tw, const double* ramp, const int32_t* qexp, float* D,
+                            TimeShape shape) {
+  const int E = (shape.E == 8 || shape.E == 16) ? shape.E : time_e(L);
+  int qpw = shape.qpw > 0 ? shape.qpw : time_qpw(L, E);
+  while (qpw > 1 && (qpw * (L / E) > 1024 || (size_t)qpw * (2 * L + L / 8 + 1) * sizeof(float2) > 160 * 1024))
+    qpw >>= 1;
   if constexpr (L >= 512) {
-    if (E == 8) return time_qpw_go<L, QB, 8>(s, qpw, spec, nq, N, M, tw, ramp, D);
+    if (E == 8) return time_qpw_go<L, QB, 8>(s, qpw, spec, nq, N, M, tw, ramp, qexp, D);
   }
-  return time_qpw_go<L, QB, 16>(s, qpw, spec, nq, N, M, tw, ramp, D);
+  return time_qpw_go<L, QB, 16>(s, qpw, spec, nq, N, M, tw, ramp, qexp, D);
 }
 
 template <int QB>
-static hipError_t time_dispatch(hipStream_t s, const float2* spec, int64_t nq, int N, int M,
-                                const float2* twN2, const double* ramp, float* D) {
+static hipError_t time_dispatch(hipStream_t s, const void* spec, int64_t nq, int N, int M,
+                                const float2* twN2, const double* ramp, const int32_t* qexp, float* D,
+                                TimeShape shape) {
   int L = 16;
   while (L < N) L <<= 1;
   switch (L) {
-    case 16: return time_e_go<16, QB>(s, spec, nq, N, M, twN2, ramp, D);
-    case 32: return time_e_go<32, QB>(s, spec, nq, N, M, twN2, ramp, D);
-    case 64: return time_e_go<64, QB>(s, spec, nq, N, M, twN2, ramp, D);
-    case 128: return time_e_go<128, QB>(s, spec, nq, N, M, twN2, ramp, D);
-    case 256: return time_e_go<256, QB>(s, spec, nq, N, M, twN2, ramp, D);
-    case 512: return time_e_go<512, QB>(s, spec, nq, N, M, twN2, ramp, D);
-    case 1024: return time_e_go<1024, QB>(s, spec, nq, N, M, twN2, ramp, D);
-    case 2048: return time_e_go<2048, QB>(s, spec, nq, N, M, twN2, ramp, D);
-    case 4096: return time_e_go<4096, QB>(s, spec, nq, N, M, twN2, ramp, D);
+    case 16: return time_e_go<16, QB>(s, spec, nq, N, M, twN2, ramp, qexp, D, shape);
+    case 32: return time_e_go<32, QB>(s, spec, nq, N, M, twN2, ramp, qexp, D, shape);
+    case 64: return time_e_go<64, QB>(s, spec, nq, N, M, twN2, ramp, qexp, D, shape);
+    case 128: return time_e_go<128, QB>(s, spec, nq, N, M, twN2, ramp, qexp, D, shape);
+    case 256: return time_e_go<256, QB>(s, spec, nq, N, M, twN2, ramp, qexp, D, shape);
+    case 512: return time_e_go<512, QB>(s, spec, nq, N, M, twN2, ramp, qexp, D, shape);
+    case 1024: return time_e_go<1024, QB>(s, spec, nq, N, M, twN2, ramp, qexp, D, shape);
+    case 2048: return time_e_go<2048, QB>(s, spec, nq, N, M, twN2, ramp, qexp, D, shape);
+    case 4096: return time_e_go<4096, QB>(s, spec, nq, N, M, twN2, ramp, qexp, D, shape);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_time(hipStream_t s, const float2* spec, int qb, int64_t nq, int N, int M,
-                       const float2* twN2, const double* ramp, float* D) {
-  if (qb == 1) return time_dispatch<1>(s, spec, nq, N, M, twN2, ramp, D);
-  if (qb == kSpecQB) return time_dispatch<kSpecQB>(s, spec, nq, N, M, twN2, ramp, D);
+hipError_t launch_time(hipStream_t s, const void* spec, int qb, int64_t nq, int N, int M,
+                       const float2* twN2, const double* ramp, const int32_t* qexp, float* D,
+                       TimeShape shape) {
+  if (qb == 1 && qexp == nullptr) return time_dispatch<1>(s, spec, nq, N, M, twN2, ramp, nullptr, D, shape);
+  if (qb == kSpecQB) return time_dispatch<kSpecQB>(s, spec, nq, N, M, twN2, ramp, qexp, D, shape);
   return hipErrorInvalidValue;
 }
 

@@ -172,7 +172,7 @@ def test_error_paths_leave_outputs_untouched(gpu):
     mn, _ = plan.workspace_size()
     small = torch.empty(mn - 256, dtype=torch.uint8, device="cuda")
     assert lib.ddm_plan_set_workspace(h, ctypes.c_void_p(small.data_ptr()), mn - 256) == L.DDM_ERR_OUT_OF_MEMORY
-    thr = np.array([0, 5, 5], dtype=np.int64)
+    thr = np.array([0, 5, 4], dtype=np.int64)  # decreasing: invalid
     out = torch.full((2, plan.max_lag), float("nan"), dtype=torch.float64, device="cuda")
     cnt = torch.full((2,), -7, dtype=torch.int64, device="cuda")
     assert lib.ddm_radial_average(h, ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(thr.ctypes.data), 2,
@@ -203,3 +203,61 @@ def test_paper_config_sampled(gpu):
     e = per_q_error(Dg[rows], Do)
     say("paper sampled:", describe(e))
     assert e.max() <= TOL_F32
+
+
+# ---- FP16 per-q-scaled spectrum store: bound 5e-3 ----
+TOL_F16 = 5e-3
+
+
+def test_fp16_plain_config(gpu):
+    say("case: FP16 store, plain 64x64x128 u8")
+    frames = synth.make(synth.PLAIN)
+    plan, Dg = run_full(gpu, frames, spectrum="f16")
+    Do, _ = oracle_D(frames.numpy())
+    e = per_q_error(Dg, Do)
+    say("plain f16:", describe(e))
+    assert e.max() <= TOL_F16
+    assert plan.fp16_saturations() == 0
+
+
+def test_fp16_group_execution_bit_identical(gpu):
+    say("case: FP16 store, group execution")
+    frames = synth.brownian_stack(128, 96, 150, 300, 1.5, 40.0, 500.0, 0.2, seed=9).cuda()
+    plan = gpu.Plan(128, 96, 150, spectrum="f16")
+    mn, full = plan.workspace_size()
+    plan.allocate_workspace(full)
+    a = plan.structure_function(frames).clone()
+    plan.allocate_workspace(mn)
+    b = plan.structure_function(frames).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_fp16_saturation_is_reported(gpu):
+    say("case: FP16 saturation warning")
+    from paper_2012_05695_amd import _lib as L
+    # static frames: the pilot frames see no change, so every scale is 2^0;
+    # a bright non-pilot frame then exceeds the FP16 range
+    frames = synth.uniform_stack(64, 64, 1, seed=2).repeat(64, 1, 1)
+    frames[5] = 4095
+    plan = gpu.Plan(64, 64, 64, spectrum="f16")
+    plan.structure_function(frames.cuda())
+    torch.cuda.synchronize()
+    assert plan.fp16_saturations() > 0
+    plan.structure_function(frames.cuda())
+    assert plan.last_status == L.DDM_WARN_FP16_SATURATED
+
+
+def test_fp16_paper_config_sampled(gpu):
+    """512x512x1024 uint16, FP16 spectra, oracle on kx columns {0,1,7,128,256}."""
+    say("case: FP16 store, paper-shaped 512x512x1024, sampled columns")
+    frames = synth.make(synth.PAPER, device="cuda")
+    plan = gpu.Plan(512, 512, 1024, spectrum="f16")
+    D = plan.structure_function(frames)
+    torch.cuda.synchronize()
+    Dg = D.cpu().numpy()
+    Do, rows = oracle_D(frames.cpu().numpy(), kx_subset=[0, 1, 7, 128, 256])
+    e = per_q_error(Dg[rows], Do)
+    say("paper f16 sampled:", describe(e))
+    assert e.max() <= TOL_F16
+    assert plan.fp16_saturations() == 0
