@@ -31,8 +31,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="paper", choices=["paper", "plain", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-columns", type=int, default=64,
-                    help="kx columns of the oracle sample (all ky, all frames, all lags)")
+    ap.add_argument("--cpu-columns", type=int, default=0,
+                    help="kx columns of the oracle sample (0: all, i.e. the whole workload)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the tau-fit leg (network training + LM vs MLP+LM on 1024x1024x2048)")
     ap.add_argument("--learned-curves", type=int, default=1_000_000)
@@ -59,12 +59,34 @@ def algorithmic_bytes(W, H, N, M, nq, pix_bytes):
     return per, whole
 
 
+def recorded_traffic(kernel, config):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary, or
+    None when there is none or the kernel sources changed since it was taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "%s_%s_f32.md" % (kernel, config))
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_t = re.search(r"^traffic_bytes_per_launch: (\d+)", text, re.M)
+    m_h = re.search(r"^source_sha256: ([0-9a-f]+)", text, re.M)
+    if not (m_t and m_h):
+        return None
+    src = "".join(open(os.path.join(ROOT, "paper_2012_05695_amd", "csrc", f)).read()
+                  for f in ("k_time.hip", "fft.hpp", "internal.hpp"))
+    if hashlib.sha256(src.encode()).hexdigest() != m_h.group(1):
+        return None
+    return int(m_t.group(1))
+
+
 def cpu_baseline(frames_cpu, ncols, nq_total):
     import numpy as np
     from oracle import dft, structure
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     fr = frames_cpu.numpy()
     N, H, W = fr.shape
+    if ncols <= 0:
+        ncols = W // 2 + 1
     cols = list(range(ncols))
     t0 = time.perf_counter()
     F = dft.dft_columns(fr, cols, np.arange(H))              # [N, H, ncols]
@@ -73,10 +95,13 @@ def cpu_baseline(frames_cpu, ncols, nq_total):
     dt = time.perf_counter() - t0
     nq_s = H * ncols
     full_s = dt * nq_total / nq_s
-    return {"value": N / full_s, "unit": "frames/s", "cores": threads, "kind": "oracle",
-            "sample": "kx columns 0..%d x all %d ky (%d of %d q), all %d frames and lags; "
-                      "%.2f s measured, extrapolated linearly in q to %.0f s" %
-                      (ncols - 1, H, nq_s, nq_total, N, dt, full_s)}
+    if nq_s >= nq_total:
+        sample = "whole workload: all %d q, all %d frames and lags (%.1f s)" % (nq_total, N, dt)
+    else:
+        sample = ("kx columns 0..%d x all %d ky (%d of %d q), all %d frames and lags; "
+                  "%.2f s measured, extrapolated linearly in q to %.0f s" %
+                  (ncols - 1, H, nq_s, nq_total, N, dt, full_s))
+    return {"value": N / full_s, "unit": "frames/s", "cores": threads, "kind": "oracle", "sample": sample}
 
 
 def learned_leg(log):
@@ -215,7 +240,9 @@ def main():
         "algorithmic_bytes_whole_path": whole,
         "kernel_ms_per_step": {k: v[0] for k, v in prof.items()},
         "roofline": {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (recorded_traffic("k_" + dominant, "%dx%dx%d" % (W, H, N))
+                                 if dominant == "time" and args.config == "paper" else None),
                      "avg_launch_ms": avg_launch_ms, "launches": k_n,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }
