@@ -180,8 +180,12 @@ ddm_status ddm_batch_structure_function(ddm_batch_t batch, const void* const* fr
  *   Dbar_dev [n_bins][M] float64: sum w D / sum w   (0 for an empty bin)
  *   counts_dev [n_bins] int64:     sum w            (full-plane lattice points)
  *   bin_of_q_dev [n_q] int32:      bin of each row of D, -1 if unbinned (may be NULL)
- * D_dev is [n_q][M] float32 as produced by ddm_structure_function.  The sums run
- * over q in q order in FP64, so results are deterministic. */
+ * D_dev is [n_q][M] float32 as produced by ddm_structure_function.  Each bin is
+ * summed in FP64 in a fixed order (its members in q order, dealt round-robin to
+ * four partial sums that are added in order), so results are deterministic.
+ * The thresholds are read before the call returns (the host array may be
+ * released then); the call waits only when they differ from the last call's
+ * and the previous radial launch of the plan is still running. */
 ddm_status ddm_radial_average(ddm_plan_t plan, const float* D_dev, const int64_t* k2_thresholds_host,
                               int32_t n_bins, double* Dbar_dev, int64_t* counts_dev,
                               int32_t* bin_of_q_dev);

@@ -79,9 +79,13 @@ struct ddm_plan_s {
   float2 *twW, *twH, *twT;
   double* ramp;  // 1/(N-m), m < N, FP64 (the ramp vector of Appendix B)
   int32_t *qoff_d, *kxcnt_d;
-  // radial thresholds (grown on demand)
+  // radial thresholds (grown on demand): device copy, pinned staging, the
+  // last values sent, and an event after the last launch that read them
   int64_t* thr_d;
+  int64_t* thr_pin;
   size_t thr_cap;
+  std::vector<int64_t> thr_last;
+  hipEvent_t thr_ev;
   // workspace
   void* ws;
   size_t ws_bytes;
@@ -286,7 +290,9 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
     return hip_fail(e, "hipMemcpy(plan tables)");
   }
   p->thr_d = nullptr;
+  p->thr_pin = nullptr;
   p->thr_cap = 0;
+  p->thr_ev = nullptr;
   p->ws = nullptr;
   p->ws_bytes = 0;
   p->prof_mask = 0;
@@ -328,6 +334,8 @@ ddm_status ddm_plan_destroy(ddm_plan_t p) {
   p->magic = 0;
   if (p->dev_tables) hipFree(p->dev_tables);
   if (p->thr_d) hipFree(p->thr_d);
+  if (p->thr_pin) hipHostFree(p->thr_pin);
+  if (p->thr_ev) hipEventDestroy(p->thr_ev);
   delete p;
   return DDM_OK;
 }
@@ -563,25 +571,42 @@ ddm_status ddm_radial_average(ddm_plan_t p, const float* D, const int64_t* thr, 
   for (int b = 0; b < n_bins; ++b)
     if (thr[b + 1] < thr[b])
       return fail(DDM_ERR_INVALID_ARGUMENT, "thresholds must be non-decreasing (at %d)", b);
-  const size_t need = (size_t)(n_bins + 1) * sizeof(int64_t);
-  if (need > p->thr_cap) {
-    hipError_t e = hipStreamSynchronize(p->stream);  // the old buffer may still be read
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    if (p->thr_d) hipFree(p->thr_d);
-    p->thr_d = nullptr;
-    p->thr_cap = 0;
-    e = hipMalloc(&p->thr_d, need);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(thresholds)");
-    p->thr_cap = need;
+  const size_t nthr = (size_t)n_bins + 1;
+  const size_t need = nthr * sizeof(int64_t);
+  hipError_t e = hipSuccess;
+  if (p->thr_ev == nullptr && (e = hipEventCreateWithFlags(&p->thr_ev, hipEventDisableTiming)) != hipSuccess) {
+    p->thr_ev = nullptr;
+    return hip_fail(e, "hipEventCreate(thresholds)");
   }
-  hipError_t e = hipMemcpyAsync(p->thr_d, thr, need, hipMemcpyHostToDevice, p->stream);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(thresholds)");
-  e = hipStreamSynchronize(p->stream);  // the host array may be released after return
-  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  // new thresholds go through the pinned buffer once the previous launch that
+  // read the device copy has finished; unchanged ones are not sent again
+  if (p->thr_last.size() != nthr || std::memcmp(p->thr_last.data(), thr, need) != 0) {
+    p->thr_last.clear();
+    if ((e = hipEventSynchronize(p->thr_ev)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    if (need > p->thr_cap) {
+      if (p->thr_d) hipFree(p->thr_d);
+      if (p->thr_pin) hipHostFree(p->thr_pin);
+      p->thr_d = nullptr;
+      p->thr_pin = nullptr;
+      p->thr_cap = 0;
+      if ((e = hipMalloc(&p->thr_d, need)) != hipSuccess) return hip_fail(e, "hipMalloc(thresholds)");
+      if ((e = hipHostMalloc((void**)&p->thr_pin, need, hipHostMallocDefault)) != hipSuccess) {
+        hipFree(p->thr_d);
+        p->thr_d = nullptr;
+        return hip_fail(e, "hipHostMalloc(thresholds)");
+      }
+      p->thr_cap = need;
+    }
+    std::memcpy(p->thr_pin, thr, need);
+    e = hipMemcpyAsync(p->thr_d, p->thr_pin, need, hipMemcpyHostToDevice, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(thresholds)");
+    p->thr_last.assign(thr, thr + nthr);
+  }
   QTable qt{p->qoff_d, p->kxcnt_d};
   ProfScope ps(p, DDM_KERNEL_RADIAL);
   e = launch_radial(p->stream, D, p->nq, p->M, p->W, p->H, p->ca, p->cc, qt, p->thr_d, n_bins, Dbar,
                     counts, bin_of_q);
+  if (e == hipSuccess) e = hipEventRecord(p->thr_ev, p->stream);
   if (e != hipSuccess) return hip_fail(e, "radial average launch");
   return DDM_OK;
 }

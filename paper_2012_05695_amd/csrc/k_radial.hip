@@ -7,12 +7,23 @@
 // contiguous kx interval [lo, hi); it is found with integer arithmetic only,
 // which makes bin membership bit-exact.
 //
-// One workgroup per (bin, lag tile); each thread owns one lag and sums
-// w(q) D(q, m) over the bin's rows in q order in FP64 (fixed order, so the
-// result is deterministic and independent of the launch geometry).
+// One workgroup per (bin, 64-lag tile).  The bin's rows are taken in chunks
+// of 256; the members of a chunk are flattened, in q order, into an LDS list
+// (q index and weight), a window of kListCap entries at a time.  Wave w of the
+// four sums the entries j = w (mod 4) of each window for its 64 lags in FP64,
+// with 16 loads in flight, and the four partials are added in wave order at
+// the end: a fixed order that depends neither on the launch geometry nor on
+// timing, so results are deterministic.
 #include "internal.hpp"
 
 namespace ddm {
+
+namespace {
+constexpr int kRadThreads = 256;
+constexpr int kRadLags = 64;
+constexpr int kListCap = 4096;
+constexpr int kUnroll = 16;
+}  // namespace
 
 // smallest kx in [0, cnt) with kx^2 * a >= r (a > 0), or cnt if none; exact
 // integer result (the floating-point root is only a starting guess).
@@ -26,80 +37,119 @@ __device__ __forceinline__ int64_t first_kx(int64_t r, int64_t a, int64_t cnt) {
   return x;
 }
 
-__global__ void __launch_bounds__(256) k_radial(const float* __restrict__ D, int M, int W, int H,
-                                                int64_t ca, int64_t cc,
-                                                const int32_t* __restrict__ qoff,
-                                                const int32_t* __restrict__ kxcnt,
-                                                const int64_t* __restrict__ thr, double* __restrict__ Dbar,
-                                                int64_t* __restrict__ counts,
-                                                int32_t* __restrict__ bin_of_q) {
+__global__ void __launch_bounds__(kRadThreads) k_radial(const float* __restrict__ D, int M, int W, int H,
+                                                        int64_t ca, int64_t cc,
+                                                        const int32_t* __restrict__ qoff,
+                                                        const int32_t* __restrict__ kxcnt,
+                                                        const int64_t* __restrict__ thr,
+                                                        double* __restrict__ Dbar,
+                                                        int64_t* __restrict__ counts,
+                                                        int32_t* __restrict__ bin_of_q) {
   const int b = blockIdx.x;
-  const int m = blockIdx.y * blockDim.x + threadIdx.x;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int m = blockIdx.y * kRadLags + lane;
+  const bool lag_ok = m < M;
+  const bool write_bins = bin_of_q != nullptr && blockIdx.y == 0;
   const int64_t lo_t = thr[b], hi_t = thr[b + 1];
-  // the bin's kx interval of every ky row, computed once per workgroup in
-  // chunks of blockDim rows and compacted (in ky order) into LDS
-  __shared__ int2 rows[256];
-  __shared__ int nrows_s;
+  const int half = W / 2;
+
+  __shared__ int32_t row_q[kRadThreads];   // q index of the row's first member
+  __shared__ int32_t row_kx[kRadThreads];  // kx of the row's first member
+  __shared__ int32_t row_off[kRadThreads + 1];
+  __shared__ int32_t wpart[4];
+  __shared__ uint32_t list[kListCap];      // q | (weight 2) << 31
+  __shared__ double part[4][kRadLags];
+  __shared__ int64_t wpart64[4];
+
   double acc = 0.0;
   int64_t wsum = 0;
-  for (int ky0 = 0; ky0 < H; ky0 += blockDim.x) {
-    if (threadIdx.x == 0) nrows_s = 0;
-    __syncthreads();
-    const int ky = ky0 + (int)threadIdx.x;
-    int2 iv = make_int2(0, 0);
+  const float* Dm = D + m;
+  for (int ky0 = 0; ky0 < H; ky0 += kRadThreads) {
+    // this thread's row: the bin's kx interval, its weight sum
+    const int ky = ky0 + tid;
+    int lo = 0, len = 0;
     if (ky < H) {
       const int64_t kys = (ky <= H / 2) ? ky : ky - H;
       const int64_t base = kys * kys * cc;
       const int64_t cnt = kxcnt[ky];
       if (cnt > 0 && base < hi_t) {
-        iv.x = (int)first_kx(lo_t - base, ca, cnt);
-        iv.y = (int)first_kx(hi_t - base, ca, cnt);
+        lo = (int)first_kx(lo_t - base, ca, cnt);
+        len = (int)first_kx(hi_t - base, ca, cnt) - lo;
+      }
+      if (len > 0) {
+        // kx in [lo, lo + len): weight 2 for 0 < kx < W/2, else 1
+        const int a = lo > 1 ? lo : 1, z = (lo + len) < half ? (lo + len) : half;
+        wsum += len + (z > a ? z - a : 0);
       }
     }
-    // compaction that keeps ky order: prefix count over the workgroup
-    const bool has = iv.x < iv.y;
-    const unsigned long long ball = __ballot(has);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    __shared__ int wcount[4];
-    if (lane == 0) wcount[wave] = __popcll(ball);
+    // exclusive prefix of the interval lengths over the workgroup (ky order)
+    int incl = len;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int v = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += v;
+    }
+    if (lane == 63) wpart[wave] = incl;
     __syncthreads();
     int before = 0;
-    for (int w = 0; w < wave; ++w) before += wcount[w];
-    before += __popcll(ball & ((1ull << lane) - 1ull));
-    if (has) rows[before] = make_int2(ky, (iv.y - iv.x) << 16 | iv.x);
-    if (threadIdx.x == blockDim.x - 1) nrows_s = before + (has ? 1 : 0);
+    for (int w = 0; w < wave; ++w) before += wpart[w];
+    const int total = wpart[0] + wpart[1] + wpart[2] + wpart[3];
+    row_off[tid] = before + incl - len;
+    row_q[tid] = (ky < H ? qoff[ky] : 0) + lo;
+    row_kx[tid] = lo;
+    if (tid == 0) row_off[kRadThreads] = total;
     __syncthreads();
-    const int nr = nrows_s;
-    for (int r = 0; r < nr; ++r) {
-    const int2 rr = rows[r];
-    const int ky_r = rr.x;
-    const int64_t lo = rr.y & 0xFFFF, hi = lo + (rr.y >> 16);
-    const int64_t q0 = qoff[ky_r];
-    for (int64_t kx = lo; kx < hi; ++kx) wsum += (kx > 0 && kx < W / 2) ? 2 : 1;
-    if (m < M) {
-      // eight rows in flight per step; the sum itself stays in q order
-      const float* col = D + (size_t)q0 * M + m;
-      int64_t kx = lo;
-      for (; kx + 8 <= hi; kx += 8) {
-        float d[8];
+    for (int s = 0; s < total; s += kListCap) {
+      const int n = (total - s) < kListCap ? (total - s) : kListCap;
+      for (int i = tid; i < n; i += kRadThreads) {
+        // row holding entry e: the last r with row_off[r] <= e (it is non-empty)
+        const int e = s + i;
+        int r0 = 0, r1 = kRadThreads;  // row_off[r0] <= e < row_off[r1]
+        while (r1 - r0 > 1) {
+          const int mid = (r0 + r1) >> 1;
+          if (row_off[mid] <= e) r0 = mid; else r1 = mid;
+        }
+        const int d = e - row_off[r0];
+        const int kx = row_kx[r0] + d;
+        const uint32_t q = (uint32_t)(row_q[r0] + d);
+        list[i] = q | ((kx > 0 && kx < half) ? 0x80000000u : 0u);
+        if (write_bins) bin_of_q[q] = b;
+      }
+      __syncthreads();
+      if (lag_ok) {
+        int j = wave;
+        for (; j + 4 * (kUnroll - 1) < n; j += 4 * kUnroll) {
+          float v[kUnroll];
+          uint32_t e[kUnroll];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) d[u] = col[(size_t)(kx + u) * M];
+          for (int u = 0; u < kUnroll; ++u) {
+            e[u] = list[j + 4 * u];
+            v[u] = Dm[(size_t)(e[u] & 0x7FFFFFFFu) * (size_t)M];
+          }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int64_t k = kx + u;
-          acc += ((k > 0 && k < W / 2) ? 2.0 : 1.0) * (double)d[u];
+          for (int u = 0; u < kUnroll; ++u) acc += ((e[u] >> 31) ? 2.0 : 1.0) * (double)v[u];
+        }
+        for (; j < n; j += 4) {
+          const uint32_t e = list[j];
+          acc += ((e >> 31) ? 2.0 : 1.0) * (double)Dm[(size_t)(e & 0x7FFFFFFFu) * (size_t)M];
         }
       }
-      for (; kx < hi; ++kx) acc += ((kx > 0 && kx < W / 2) ? 2.0 : 1.0) * (double)col[(size_t)kx * M];
+      __syncthreads();  // list[] is rewritten by the next window
     }
-    if (bin_of_q != nullptr && blockIdx.y == 0) {
-      for (int64_t kx = lo + threadIdx.x; kx < hi; kx += blockDim.x) bin_of_q[q0 + kx] = b;
-    }
-    }
-    __syncthreads();  // rows[] is rewritten by the next chunk
   }
-  if (m < M) Dbar[(size_t)b * M + m] = (wsum > 0) ? acc / (double)wsum : 0.0;
-  if (blockIdx.y == 0 && threadIdx.x == 0) counts[b] = wsum;
+  // partials of the four waves, added in wave order; weight sum over threads
+  part[wave][lane] = acc;
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) wsum += __shfl_xor(wsum, d, 64);
+  if (lane == 0) wpart64[wave] = wsum;
+  __syncthreads();
+  if (wave == 0) {
+    const int64_t ws = wpart64[0] + wpart64[1] + wpart64[2] + wpart64[3];
+    const double sum = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+    if (lag_ok) Dbar[(size_t)b * M + m] = (ws > 0) ? sum / (double)ws : 0.0;
+    if (blockIdx.y == 0 && lane == 0) counts[b] = ws;
+  }
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
@@ -116,9 +166,8 @@ hipError_t launch_radial(hipStream_t s, const float* D, int64_t nq, int M, int W
     if (e != hipSuccess) return e;
   }
   if (nbins == 0) return hipSuccess;
-  const int mt = 256;
-  dim3 grid(nbins, (M + mt - 1) / mt);
-  hipLaunchKernelGGL(k_radial, grid, dim3(mt), 0, s, D, M, W, H, ca, cc, qt.qoff, qt.kxcnt, thr,
+  dim3 grid(nbins, (M + kRadLags - 1) / kRadLags);
+  hipLaunchKernelGGL(k_radial, grid, dim3(kRadThreads), 0, s, D, M, W, H, ca, cc, qt.qoff, qt.kxcnt, thr,
                      Dbar, counts, bin_of_q);
   return hipGetLastError();
 }

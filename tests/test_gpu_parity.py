@@ -157,6 +157,35 @@ def test_radial_average(gpu, W, H):
     assert rel[counts.cpu().numpy() > 0].max() <= TOL_F32
 
 
+def test_radial_wide_bins_and_threshold_reuse(gpu):
+    """384x384 (two 256-row chunks), 70 lags (a partial second lag tile), a bin
+    with ~70k members (many list windows), an empty bin; the same thresholds
+    again (no new copy) and then new ones; reruns are bit-identical."""
+    say("case: radial wide bins 384x384x70")
+    W = H = 384
+    frames = synth.uniform_stack(W, H, 70, seed=9, pixel="u8")
+    plan, Dg = run_full(gpu, frames)
+    kx, ky = plan.q_index()
+    k2max = int(dft.k2_of(kx, ky, W, H).max())
+    D = torch.from_numpy(Dg).cuda()
+    Ts = [np.array([0, 10, 10, 1000, k2max + 1], dtype=np.int64),
+          np.array([0, 10, 10, 1000, k2max + 1], dtype=np.int64),
+          np.array([3, 4000, 4001, 90000], dtype=np.int64)]
+    first = None
+    for i, T in enumerate(Ts):
+        Dbar, counts, boq = plan.radial_average(D, T)
+        torch.cuda.synchronize()
+        Do_bar, Do_counts, Do_b = radial.radial_average(Dg.astype(np.float64), kx, ky, W, H, T)
+        np.testing.assert_array_equal(boq.cpu().numpy(), Do_b)
+        np.testing.assert_array_equal(counts.cpu().numpy(), Do_counts)
+        np.testing.assert_allclose(Dbar.cpu().numpy(), Do_bar, rtol=1e-12, atol=0)
+        if i == 0:
+            assert Do_counts[1] == 0 and Do_counts[3] > 4 * 4096
+            first = Dbar.clone()
+        if i == 1:
+            assert torch.equal(Dbar, first)
+
+
 def test_error_paths_leave_outputs_untouched(gpu):
     say("case: error paths")
     from paper_2012_05695_amd import _lib as L
