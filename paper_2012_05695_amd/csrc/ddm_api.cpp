@@ -71,6 +71,7 @@ struct ddm_plan_s {
   int64_t ca, cc;  // k2 = kx^2 ca + ky_s^2 cc
   std::vector<int32_t> qoff, kxcnt;
   int kx_needed, cw, kxw, ncol_tiles;
+  int kxnyq;  // W/2 when the Nyquist column is kept (packed with kx = 0), else -1
   size_t frame_inter_bytes;
   int fb_target;
   hipStream_t stream;
@@ -79,6 +80,12 @@ struct ddm_plan_s {
   float2 *twW, *twH, *twT;
   double* ramp;  // 1/(N-m), m < N, FP64 (the ramp vector of Appendix B)
   int32_t *qoff_d, *kxcnt_d;
+  // blocked spectra store: slot tables (every row starts a new block of 16,
+  // the Nyquist column has its own rows of blocks), slot -> wave vector
+  int64_t nslots;
+  int sN;
+  std::vector<int32_t> sbase;
+  int32_t *sbase_d, *qmap_d;
   // radial thresholds (grown on demand): device copy, pinned staging, the
   // last values sent, and an event after the last launch that read them
   int64_t* thr_d;
@@ -252,10 +259,43 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
   p->kx_needed = kxn;
   const ColCfg cc = col_cfg(H);
   p->cw = cc.cw;
-  p->ncol_tiles = (kxn + p->cw - 1) / p->cw;
+  // the real columns kx = 0 and kx = W/2 share one complex column when both are kept
+  p->kxnyq = (kxn == W / 2 + 1) ? W / 2 : -1;
+  const int ncols = p->kxnyq > 0 ? W / 2 : kxn;
+  p->ncol_tiles = (ncols + p->cw - 1) / p->cw;
   p->kxw = p->ncol_tiles * p->cw;
   p->frame_inter_bytes = (size_t)H * p->kxw * sizeof(float2);
   p->fb_target = (int)std::max<size_t>(1, std::min<size_t>(N, kInterTargetBytes / p->frame_inter_bytes));
+  // Slots of the blocked store: the kept kx < KR of row ky fill slots
+  // sbase[ky] + kx, each row rounded up to whole blocks, so that a column tile
+  // of 16 writes whole 128-byte lines; packed Nyquist values (ky, W/2) follow
+  // in slots sN + ky.
+  {
+    const int KR = p->kxnyq > 0 ? W / 2 : kxn;
+    p->sbase.assign(H, 0);
+    int64_t acc = 0;
+    for (int ky = 0; ky < H; ++ky) {
+      p->sbase[ky] = (int32_t)acc;
+      const int r = std::min(p->kxcnt[ky], KR);
+      acc += (r + kSpecQB - 1) / kSpecQB * kSpecQB;
+    }
+    p->sN = -1;
+    if (p->kxnyq > 0) {
+      p->sN = (int)acc;
+      acc += (H + kSpecQB - 1) / kSpecQB * kSpecQB;
+    }
+    p->nslots = acc;
+  }
+  if (p->nslots > INT32_MAX) {
+    delete p;
+    return fail(DDM_ERR_UNSUPPORTED, "too many wave vectors");
+  }
+  std::vector<int32_t> qmap((size_t)p->nslots, -1);
+  for (int ky = 0; ky < H; ++ky) {
+    const int r = std::min(p->kxcnt[ky], p->kxnyq > 0 ? W / 2 : kxn);
+    for (int kx = 0; kx < r; ++kx) qmap[(size_t)p->sbase[ky] + kx] = p->qoff[ky] + kx;
+    if (p->kxnyq > 0 && p->kxcnt[ky] == W / 2 + 1) qmap[(size_t)p->sN + ky] = p->qoff[ky] + W / 2;
+  }
   p->stream = (hipStream_t)desc->stream;
 
   // device tables: twiddles for W, H, 2L; q offsets and counts per ky row
@@ -268,7 +308,8 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
   const size_t ramp_bytes = align256((size_t)N * sizeof(double));
   std::vector<double> ramp(N);
   for (int m = 0; m < N; ++m) ramp[m] = 1.0 / (double)(N - m);
-  const size_t tab_bytes = tw_bytes + ramp_bytes + 2 * align256(H * sizeof(int32_t));
+  const size_t qmap_bytes = align256((size_t)p->nslots * sizeof(int32_t));
+  const size_t tab_bytes = tw_bytes + ramp_bytes + 3 * align256(H * sizeof(int32_t)) + qmap_bytes;
   hipError_t e = hipMalloc(&p->dev_tables, tab_bytes);
   if (e != hipSuccess) {
     delete p;
@@ -281,10 +322,15 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
   p->ramp = (double*)(base + tw_bytes);
   p->qoff_d = (int32_t*)(base + tw_bytes + ramp_bytes);
   p->kxcnt_d = (int32_t*)(base + tw_bytes + ramp_bytes + align256(H * sizeof(int32_t)));
+  p->sbase_d = (int32_t*)(base + tw_bytes + ramp_bytes + 2 * align256(H * sizeof(int32_t)));
+  p->qmap_d = (int32_t*)(base + tw_bytes + ramp_bytes + 3 * align256(H * sizeof(int32_t)));
   if ((e = hipMemcpy(p->twW, tw.data(), ntw * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(p->ramp, ramp.data(), N * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(p->qoff_d, p->qoff.data(), H * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(p->kxcnt_d, p->kxcnt.data(), H * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess) {
+      (e = hipMemcpy(p->kxcnt_d, p->kxcnt.data(), H * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(p->sbase_d, p->sbase.data(), H * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(p->qmap_d, qmap.data(), (size_t)p->nslots * sizeof(int32_t), hipMemcpyHostToDevice)) !=
+          hipSuccess) {
     hipFree(p->dev_tables);
     delete p;
     return hip_fail(e, "hipMemcpy(plan tables)");
@@ -366,7 +412,7 @@ ddm_status ddm_plan_q_index(ddm_plan_t p, int32_t* kx_host, int32_t* ky_signed_h
 
 static size_t spec_elem_bytes(const ddm_plan_s* p) { return p->f16 ? 4 : sizeof(float2); }
 static size_t spec_block_bytes(const ddm_plan_s* p) { return (size_t)p->N * kSpecQB * spec_elem_bytes(p); }
-static int64_t n_spec_blocks(const ddm_plan_s* p) { return (p->nq + kSpecQB - 1) / kSpecQB; }
+static int64_t n_spec_blocks(const ddm_plan_s* p) { return p->nslots / kSpecQB; }
 // FP16 store only: pilot spectra [nq][np], per-q exponents, saturation counter
 static size_t aux_bytes(const ddm_plan_s* p) {
   if (!p->f16) return 0;
@@ -423,23 +469,25 @@ static void partition(const ddm_plan_s* p, int* fb, int64_t* gblocks) {
   *gblocks = g;
 }
 
-// Step one for frames [0, N) into the spectra of q in [q_lo, q_hi).
-static ddm_status run_step_one(ddm_plan_s* p, const void* frames, float2* inter, int fb, int64_t q_lo,
-                               int64_t q_hi, int qb, SpecOut out) {
+// Step one for frames 0..N-1 into slots [s_lo, s_hi): the blocked store
+// (qb = 16, the plan's slot tables) or the plain [q][N] layout (qb = 1, slot = q).
+static ddm_status run_step_one(ddm_plan_s* p, const void* frames, float2* inter, int fb, int64_t s_lo,
+                               int64_t s_hi, int qb, SpecOut out) {
   QTable qt{p->qoff_d, p->kxcnt_d};
+  const SlotMap sm = (qb == 1) ? SlotMap{p->qoff_d, -1} : SlotMap{p->sbase_d, p->sN};
   for (int t0 = 0; t0 < p->N; t0 += fb) {
     const int nf = std::min(fb, p->N - t0);
     hipError_t e;
     {
       ProfScope ps(p, DDM_KERNEL_ROW);
       e = launch_row(p->stream, p->d.pixel, frames, p->W, p->H, t0, nf, p->d.precondition,
-                     inter, p->kxw, p->twW, 1);
+                     inter, p->kxw, p->kxnyq > 0, p->twW, 1);
     }
     if (e != hipSuccess) return hip_fail(e, "row transform launch");
     {
       ProfScope ps(p, DDM_KERNEL_COL);
-      e = launch_col(p->stream, inter, p->H, p->kxw, p->ncol_tiles, t0, nf, p->N, qt, q_lo, q_hi, qb,
-                     out, p->twH, 1);
+      e = launch_col(p->stream, inter, p->H, p->kxw, p->ncol_tiles, t0, nf, p->N, qt, sm, s_lo, s_hi, qb,
+                     p->kxnyq, out, p->twH, 1);
     }
     if (e != hipSuccess) return hip_fail(e, "column transform launch");
   }
@@ -454,10 +502,10 @@ static ddm_status run_pilot(ddm_plan_s* p, const void* frames, float2* inter, fl
   const int np = (int)p->pilot.size();
   for (int i = 0; i < np; ++i) {
     hipError_t e = launch_row(p->stream, p->d.pixel, frames, p->W, p->H, p->pilot[i], 1, p->d.precondition,
-                              inter, p->kxw, p->twW, 1);
+                              inter, p->kxw, p->kxnyq > 0, p->twW, 1);
     if (e == hipSuccess)
-      e = launch_col(p->stream, inter, p->H, p->kxw, p->ncol_tiles, i, 1, np, qt, 0, p->nq, 1,
-                     SpecOut{pilot, nullptr, nullptr}, p->twH, 1);
+      e = launch_col(p->stream, inter, p->H, p->kxw, p->ncol_tiles, i, 1, np, qt, SlotMap{p->qoff_d, -1}, 0,
+                     p->nq, 1, p->kxnyq, SpecOut{pilot, nullptr, nullptr}, p->twH, 1);
     if (e != hipSuccess) return hip_fail(e, "pilot transform launch");
   }
   hipError_t e = launch_qexp(p->stream, pilot, np, p->nq, qexp);
@@ -502,15 +550,15 @@ ddm_status ddm_structure_function(ddm_plan_t p, const void* frames, float* D) {
     st = run_pilot(p, frames, inter, pilot, qexp, sat);
     if (st != DDM_OK) return st;
   }
-  const int64_t gq = gblocks * kSpecQB;
-  for (int64_t q_lo = 0; q_lo < p->nq; q_lo += gq) {
-    const int64_t q_hi = std::min(p->nq, q_lo + gq);
-    st = run_step_one(p, frames, inter, fb, q_lo, q_hi, kSpecQB, SpecOut{spec, qexp, sat});
+  const int64_t gs = gblocks * kSpecQB;
+  for (int64_t s_lo = 0; s_lo < p->nslots; s_lo += gs) {
+    const int64_t s_hi = std::min(p->nslots, s_lo + gs);
+    st = run_step_one(p, frames, inter, fb, s_lo, s_hi, kSpecQB, SpecOut{spec, qexp, sat});
     if (st != DDM_OK) return st;
     {
       ProfScope ps(p, DDM_KERNEL_TIME);
-      e = launch_time(p->stream, spec, kSpecQB, q_hi - q_lo, p->N, p->M, p->twT, p->ramp,
-                      qexp ? qexp + q_lo : nullptr, D + (size_t)q_lo * p->M, p->tshape);
+      e = launch_time(p->stream, spec, kSpecQB, s_hi - s_lo, p->N, p->M, p->twT, p->ramp, p->qmap_d + s_lo,
+                      qexp, D, p->tshape);
     }
     if (e != hipSuccess) return hip_fail(e, "time transform launch");
   }
@@ -553,7 +601,7 @@ ddm_status ddm_structure_from_spectra(ddm_plan_t p, const float* spectra, float*
   hipError_t e;
   {
     ProfScope ps(p, DDM_KERNEL_TIME);
-    e = launch_time(p->stream, spectra, 1, p->nq, p->N, p->M, p->twT, p->ramp, nullptr, D, p->tshape);
+    e = launch_time(p->stream, spectra, 1, p->nq, p->N, p->M, p->twT, p->ramp, nullptr, nullptr, D, p->tshape);
   }
   if (e != hipSuccess) return hip_fail(e, "time transform launch");
   return DDM_OK;
@@ -765,10 +813,10 @@ ddm_status ddm_plan_autotune(ddm_plan_t p, int32_t* E_out, int32_t* qpw_out, dou
         if (p->L / E < 1 || p->L % E != 0 || (E == 8 && p->L < 512)) continue;
         if (qpw * (p->L / E) > 1024 || (size_t)qpw * (2 * p->L + p->L / 8 + 1) * 8 > 160 * 1024) continue;
         const TimeShape sh{E, qpw};
-        e = launch_time(p->stream, spec, kSpecQB, nq_t, p->N, p->M, p->twT, p->ramp, qexp, dout, sh);
+        e = launch_time(p->stream, spec, kSpecQB, nq_t, p->N, p->M, p->twT, p->ramp, nullptr, qexp, dout, sh);
         if (e == hipSuccess) e = hipEventRecord(a, p->stream);
         for (int r = 0; r < 2 && e == hipSuccess; ++r)
-          e = launch_time(p->stream, spec, kSpecQB, nq_t, p->N, p->M, p->twT, p->ramp, qexp, dout, sh);
+          e = launch_time(p->stream, spec, kSpecQB, nq_t, p->N, p->M, p->twT, p->ramp, nullptr, qexp, dout, sh);
         if (e == hipSuccess) e = hipEventRecord(b, p->stream);
         if (e == hipSuccess) e = hipEventSynchronize(b);
         float ms = 0.f;
@@ -782,7 +830,7 @@ ddm_status ddm_plan_autotune(ddm_plan_t p, int32_t* E_out, int32_t* qpw_out, dou
     if (a) hipEventDestroy(a);
     if (b) hipEventDestroy(b);
     if (e != hipSuccess) return hip_fail(e, "autotune");
-    best_ms = best_ms / 2.0 * ((double)p->nq / (double)nq_t);  // per launch over all q
+    best_ms = best_ms / 2.0 * ((double)p->nslots / (double)nq_t);  // per launch over all slots
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune[key] = std::make_tuple(best.E, best.qpw, best_ms);
   }

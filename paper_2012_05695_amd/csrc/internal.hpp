@@ -69,8 +69,9 @@ enum : int32_t {
 };
 
 // ---- launchers (each returns hipSuccess or the launch error) ----
+// pack: slot 0 of every row carries R(0) + i R(W/2) (the Nyquist column is needed).
 hipError_t launch_row(hipStream_t s, int pixel, const void* frames, int W, int H, int64_t t0,
-                      int nframes, int precondition, float2* inter, int kxw,
+                      int nframes, int precondition, float2* inter, int kxw, int pack,
                       const float2* tw, int tws);
 
 // Destination of the column transform: complex FP32, or complex FP16 scaled
@@ -81,15 +82,28 @@ struct SpecOut {
   int32_t* sat;
 };
 
+// Slot of each kept wave vector in the spectra store: (ky, kx < W/2, or any
+// kept kx without packing) -> sbase[ky] + kx; the Nyquist value (ky, W/2) ->
+// sN + ky, or sbase[ky] + W/2 when sN < 0.  The plain layout is sbase = qoff.
+struct SlotMap {
+  const int32_t* sbase;  // [H] (device)
+  int sN;
+};
+
+// Writes slots [s_lo, s_hi) of frames t0..t0+nframes-1.  qb: 16 (the blocked
+// store) or 1 (plain [slot][N]); kxnyq: W/2 when the rows are packed, else -1.
+// Slot and q indices must fit in int32.
 hipError_t launch_col(hipStream_t s, const float2* inter, int H, int kxw, int ntiles,
-                      int64_t t0, int nframes, int N, QTable qt, int64_t q_lo, int64_t q_hi,
-                      int qb, SpecOut out, const float2* tw, int tws);
+                      int64_t t0, int nframes, int N, QTable qt, SlotMap sm, int64_t s_lo, int64_t s_hi,
+                      int qb, int kxnyq, SpecOut out, const float2* tw, int tws);
 
 hipError_t launch_qexp(hipStream_t s, const float2* pilot, int np, int64_t nq, int32_t* qexp);
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
 
-// spec: complex FP32, or complex FP16 scaled by 2^qexp[q] when qexp is non-null
-// (qexp indexed by the group-local q).
+// spec: the group's slots, complex FP32, or complex FP16 scaled by 2^qexp[q]
+// when qexp is non-null (qexp indexed by wave vector q).  qmap: wave vector of
+// each of the group's slots (-1: none), or null when slot s is wave vector s;
+// D_rows + q M is the output row of wave vector q.
 // Launch shape of the time kernel: values per thread E (8 or 16) and wave
 // vectors per workgroup; 0 picks the built-in choice for the length.
 struct TimeShape {
@@ -97,8 +111,9 @@ struct TimeShape {
   int qpw = 0;
 };
 
-hipError_t launch_time(hipStream_t s, const void* spec, int qb, int64_t nq_group, int N, int M,
-                       const float2* twN2, const double* ramp, const int32_t* qexp, float* D_rows,
+hipError_t launch_time(hipStream_t s, const void* spec, int qb, int64_t nslots_group, int N, int M,
+                       const float2* twN2, const double* ramp, const int32_t* qmap,
+                       const int32_t* qexp, float* D_rows,
                        TimeShape shape = TimeShape{});
 
 hipError_t launch_radial(hipStream_t s, const float* D, int64_t nq, int M, int W, int H,

@@ -112,14 +112,17 @@ __device__ __forceinline__ double group_excl_scan(double v, int tid, double* scr
 
 }  // namespace
 
-// QB: layout of the input time series.  QB == 1: plain q-major [q][N].
-// QB > 1: the blocked store [q / QB][N][QB] written by the column transform.
+// QB: layout of the input time series, indexed by slot s < nq.  QB == 1:
+// plain [s][N].  QB > 1: the blocked store [s / QB][N][QB] written by the
+// column transform.  qmap[s] is the wave vector (row of D) held by slot s, -1
+// for a slot that holds none; a null qmap means slot s holds wave vector s.
 // F16 (blocked store only): complex FP16 scaled by 2^qexp[q], unscaled on load
 // (exact: a power of two).
 template <int L, int QPW, int QB, int E, bool TWL, bool F16>
 __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__ spec, int64_t nq,
                                                        int N, int M, const float2* __restrict__ twN2,
                                                        const double* __restrict__ ramp,
+                                                       const int32_t* __restrict__ qmap,
                                                        const int32_t* __restrict__ qexp,
                                                        float* __restrict__ D) {
   constexpr int T = L / E;
@@ -173,8 +176,9 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
     }
     float sc = 1.0f;  // 2^-qexp of this thread's wave vector (blocked layout: i = threadIdx.x % QPW)
     if constexpr (F16) {
-      const int64_t qq = q0 + (threadIdx.x % QPW);
-      sc = (qq < nq) ? ldexpf(1.0f, -qexp[qq]) : 1.0f;
+      const int64_t ss = q0 + (threadIdx.x % QPW);
+      const int qq = (ss < nq) ? (qmap ? qmap[ss] : (int)ss) : -1;
+      sc = (qq >= 0) ? ldexpf(1.0f, -qexp[qq]) : 1.0f;
     }
     float2 ld[E];
 #pragma unroll
@@ -209,7 +213,8 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
 
   const int qi = threadIdx.x / T;
   const int tid = threadIdx.x % T;
-  const int64_t q = q0 + qi;
+  const int64_t q = q0 + qi;  // slot of this wave vector in the store
+  const int qd = (q < nq) ? (qmap ? qmap[q] : (int)q) : -1;  // its row of D (-1: a hole)
   LdsView<1, true> xb{xall + qi * XS};
   LdsView<1, true> yb{yall + qi * YS};
   double* xd = reinterpret_cast<double*>(xall + qi * XS);  // the same bytes, as doubles
@@ -285,10 +290,10 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
   group_sync<WAVE>();
 
   // ---- D(m) = (S(N-m) + S(N) - S(m) - 2 Re c(m)) / (N-m) ----
-  if (q < nq) {
+  if (qd >= 0) {
     const double sN = xd[LdsView<1, true>::slot(N)];
     const float inv_l = 1.0f / (float)L;  // 2 / N2, exact
-    float* drow = D + (size_t)q * M;
+    float* drow = D + (size_t)qd * M;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int m = tid + e * T;
@@ -353,7 +358,7 @@ static bool time_twl() {
 
 template <int L, int QPW, int QB, int E>
 static hipError_t time_go(hipStream_t s, const void* spec, int64_t nq, int N, int M,
-                          const float2* tw, const double* ramp, const int32_t* qexp, float* D) {
+                          const float2* tw, const double* ramp, const int32_t* qmap, const int32_t* qexp, float* D) {
   int64_t nwg;
   if (QPW >= QB) {
     nwg = (nq + QPW - 1) / QPW;
@@ -368,24 +373,24 @@ static hipError_t time_go(hipStream_t s, const void* spec, int64_t nq, int N, in
       if constexpr (QB > 1) {
         if (qexp != nullptr) {
           hipLaunchKernelGGL((k_time<L, QPW, QB, E, true, true>), grid, block, 0, s, spec, nq, N, M, tw, ramp,
-                             qexp, D);
+                             qmap, qexp, D);
           return hipGetLastError();
         }
       }
       hipLaunchKernelGGL((k_time<L, QPW, QB, E, true, false>), grid, block, 0, s, spec, nq, N, M, tw, ramp,
-                         nullptr, D);
+                         qmap, nullptr, D);
       return hipGetLastError();
     }
   }
   if constexpr (QB > 1) {
     if (qexp != nullptr) {
       hipLaunchKernelGGL((k_time<L, QPW, QB, E, false, true>), grid, block, 0, s, spec, nq, N, M, tw, ramp,
-                         qexp, D);
+                         qmap, qexp, D);
       return hipGetLastError();
     }
   }
   hipLaunchKernelGGL((k_time<L, QPW, QB, E, false, false>), grid, block, 0, s, spec, nq, N, M, tw, ramp,
-                     nullptr, D);
+                     qmap, nullptr, D);
   return hipGetLastError();
 }
 
@@ -396,60 +401,60 @@ static constexpr bool qpw_fits() {
 
 template <int L, int QB, int E>
 static hipError_t time_qpw_go(hipStream_t s, int qpw, const void* spec, int64_t nq, int N, int M,
-                              const float2* tw, const double* ramp, const int32_t* qexp, float* D) {
+                              const float2* tw, const double* ramp, const int32_t* qmap, const int32_t* qexp, float* D) {
   switch (qpw) {
-    case 16: if constexpr (qpw_fits<L, 16, E>()) return time_go<L, 16, QB, E>(s, spec, nq, N, M, tw, ramp, qexp, D);
+    case 16: if constexpr (qpw_fits<L, 16, E>()) return time_go<L, 16, QB, E>(s, spec, nq, N, M, tw, ramp, qmap, qexp, D);
              break;
-    case 8: if constexpr (qpw_fits<L, 8, E>()) return time_go<L, 8, QB, E>(s, spec, nq, N, M, tw, ramp, qexp, D);
+    case 8: if constexpr (qpw_fits<L, 8, E>()) return time_go<L, 8, QB, E>(s, spec, nq, N, M, tw, ramp, qmap, qexp, D);
             break;
-    case 4: if constexpr (qpw_fits<L, 4, E>()) return time_go<L, 4, QB, E>(s, spec, nq, N, M, tw, ramp, qexp, D);
+    case 4: if constexpr (qpw_fits<L, 4, E>()) return time_go<L, 4, QB, E>(s, spec, nq, N, M, tw, ramp, qmap, qexp, D);
             break;
-    case 2: if constexpr (qpw_fits<L, 2, E>()) return time_go<L, 2, QB, E>(s, spec, nq, N, M, tw, ramp, qexp, D);
+    case 2: if constexpr (qpw_fits<L, 2, E>()) return time_go<L, 2, QB, E>(s, spec, nq, N, M, tw, ramp, qmap, qexp, D);
             break;
-    case 1: return time_go<L, 1, QB, E>(s, spec, nq, N, M, tw, ramp, qexp, D);
+    case 1: return time_go<L, 1, QB, E>(s, spec, nq, N, M, tw, ramp, qmap, qexp, D);
   }
   return hipErrorInvalidValue;
 }
 
 template <int L, int QB>
 static hipError_t time_e_go(hipStream_t s, const void* spec, int64_t nq, int N, int M,
-                            const float2* tw, const double* ramp, const int32_t* qexp, float* D,
+                            const float2* tw, const double* ramp, const int32_t* qmap, const int32_t* qexp, float* D,
                             TimeShape shape) {
   const int E = (shape.E == 8 || shape.E == 16) ? shape.E : time_e(L);
   int qpw = shape.qpw > 0 ? shape.qpw : time_qpw(L, E);
   while (qpw > 1 && (qpw * (L / E) > 1024 || (size_t)qpw * (2 * L + L / 8 + 1) * sizeof(float2) > 160 * 1024))
     qpw >>= 1;
   if constexpr (L >= 512) {
-    if (E == 8) return time_qpw_go<L, QB, 8>(s, qpw, spec, nq, N, M, tw, ramp, qexp, D);
+    if (E == 8) return time_qpw_go<L, QB, 8>(s, qpw, spec, nq, N, M, tw, ramp, qmap, qexp, D);
   }
-  return time_qpw_go<L, QB, 16>(s, qpw, spec, nq, N, M, tw, ramp, qexp, D);
+  return time_qpw_go<L, QB, 16>(s, qpw, spec, nq, N, M, tw, ramp, qmap, qexp, D);
 }
 
 template <int QB>
 static hipError_t time_dispatch(hipStream_t s, const void* spec, int64_t nq, int N, int M,
-                                const float2* twN2, const double* ramp, const int32_t* qexp, float* D,
+                                const float2* twN2, const double* ramp, const int32_t* qmap, const int32_t* qexp, float* D,
                                 TimeShape shape) {
   int L = 16;
   while (L < N) L <<= 1;
   switch (L) {
-    case 16: return time_e_go<16, QB>(s, spec, nq, N, M, twN2, ramp, qexp, D, shape);
-    case 32: return time_e_go<32, QB>(s, spec, nq, N, M, twN2, ramp, qexp, D, shape);
-    case 64: return time_e_go<64, QB>(s, spec, nq, N, M, twN2, ramp, qexp, D, shape);
-    case 128: return time_e_go<128, QB>(s, spec, nq, N, M, twN2, ramp, qexp, D, shape);
-    case 256: return time_e_go<256, QB>(s, spec, nq, N, M, twN2, ramp, qexp, D, shape);
-    case 512: return time_e_go<512, QB>(s, spec, nq, N, M, twN2, ramp, qexp, D, shape);
-    case 1024: return time_e_go<1024, QB>(s, spec, nq, N, M, twN2, ramp, qexp, D, shape);
-    case 2048: return time_e_go<2048, QB>(s, spec, nq, N, M, twN2, ramp, qexp, D, shape);
-    case 4096: return time_e_go<4096, QB>(s, spec, nq, N, M, twN2, ramp, qexp, D, shape);
+    case 16: return time_e_go<16, QB>(s, spec, nq, N, M, twN2, ramp, qmap, qexp, D, shape);
+    case 32: return time_e_go<32, QB>(s, spec, nq, N, M, twN2, ramp, qmap, qexp, D, shape);
+    case 64: return time_e_go<64, QB>(s, spec, nq, N, M, twN2, ramp, qmap, qexp, D, shape);
+    case 128: return time_e_go<128, QB>(s, spec, nq, N, M, twN2, ramp, qmap, qexp, D, shape);
+    case 256: return time_e_go<256, QB>(s, spec, nq, N, M, twN2, ramp, qmap, qexp, D, shape);
+    case 512: return time_e_go<512, QB>(s, spec, nq, N, M, twN2, ramp, qmap, qexp, D, shape);
+    case 1024: return time_e_go<1024, QB>(s, spec, nq, N, M, twN2, ramp, qmap, qexp, D, shape);
+    case 2048: return time_e_go<2048, QB>(s, spec, nq, N, M, twN2, ramp, qmap, qexp, D, shape);
+    case 4096: return time_e_go<4096, QB>(s, spec, nq, N, M, twN2, ramp, qmap, qexp, D, shape);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_time(hipStream_t s, const void* spec, int qb, int64_t nq, int N, int M,
-                       const float2* twN2, const double* ramp, const int32_t* qexp, float* D,
+                       const float2* twN2, const double* ramp, const int32_t* qmap, const int32_t* qexp, float* D,
                        TimeShape shape) {
-  if (qb == 1 && qexp == nullptr) return time_dispatch<1>(s, spec, nq, N, M, twN2, ramp, nullptr, D, shape);
-  if (qb == kSpecQB) return time_dispatch<kSpecQB>(s, spec, nq, N, M, twN2, ramp, qexp, D, shape);
+  if (qb == 1 && qexp == nullptr) return time_dispatch<1>(s, spec, nq, N, M, twN2, ramp, qmap, nullptr, D, shape);
+  if (qb == kSpecQB) return time_dispatch<kSpecQB>(s, spec, nq, N, M, twN2, ramp, qmap, qexp, D, shape);
   return hipErrorInvalidValue;
 }
 
