@@ -150,10 +150,10 @@ template <bool WAVE> __device__ __forceinline__ void group_sync() {
 
 // Pass of radix R with span NS (product of the radices already applied).
 // Exchanges through LDS unless it is the last pass.  Every thread of the
-// workgroup must call it (it contains __syncthreads()).
-template <int L, int E, int R, int NS, int STR, bool PAD, bool WAVE>
-__device__ __forceinline__ void stockham_pass(float2 (&v)[E], LdsView<STR, PAD> buf, int tid,
-                                              const float2* __restrict__ tw, int tws) {
+// workgroup must call it (it contains __syncthreads()).  twf(b, k, jm) gives
+// the twiddle exp(-2 pi i k jm / (NS R)) of butterfly b of this thread.
+template <int L, int E, int R, int NS, int STR, bool PAD, bool WAVE, typename TwF>
+__device__ __forceinline__ void stockham_pass_g(float2 (&v)[E], LdsView<STR, PAD> buf, int tid, TwF twf) {
   constexpr int T = L / E;
   constexpr int NB = E / R;
   constexpr bool LAST = (NS * R == L);
@@ -165,9 +165,8 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[E], LdsView<STR, PAD> 
     for (int k = 0; k < R; ++k) x[k] = v[b + k * NB];
     const int jm = (NS == 1) ? 0 : (j % NS);
     if (NS > 1) {
-      const int step = jm * (L / (NS * R)) * tws;
 #pragma unroll
-      for (int k = 1; k < R; ++k) x[k] = cmul(x[k], tw[k * step]);
+      for (int k = 1; k < R; ++k) x[k] = cmul(x[k], twf(b, k, jm));
     }
     Dft<R>::run(x);
     if (LAST) {
@@ -185,6 +184,14 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[E], LdsView<STR, PAD> 
     for (int e = 0; e < E; ++e) v[e] = buf[tid + e * T];
     group_sync<WAVE>();
   }
+}
+
+// Twiddles from a table tw[j] = exp(-2 pi i j / L_tab), read at stride tws = L_tab / L.
+template <int L, int E, int R, int NS, int STR, bool PAD, bool WAVE>
+__device__ __forceinline__ void stockham_pass(float2 (&v)[E], LdsView<STR, PAD> buf, int tid,
+                                              const float2* __restrict__ tw, int tws) {
+  stockham_pass_g<L, E, R, NS, STR, PAD, WAVE>(
+      v, buf, tid, [&](int, int k, int jm) { return tw[k * jm * (L / (NS * R)) * tws]; });
 }
 
 template <int L, int E, int NS, int STR, bool PAD, bool WAVE>
@@ -205,6 +212,69 @@ __device__ __forceinline__ void fft_forward(float2 (&v)[E], LdsView<STR, PAD> bu
   static_assert(L % E == 0, "E must divide L");
   static_assert(fft_schedule_ok(L, E), "no radix schedule");
   FftPasses<L, E, 1, STR, PAD, WAVE>::run(v, buf, tid, tw, tws);
+}
+
+// The twiddles of every pass of a length-L transform, held in registers by
+// the thread that applies them: for kernels that run several transforms with
+// the same thread layout, they are fetched once instead of once per pass.
+// Pass (R, NS) of butterfly j = tid + b*T uses exp(-2 pi i k (j mod NS) / (NS R)),
+// k = 1..R-1.
+template <int L, int E, int NS = 1, bool DONE = (NS == L)>
+struct TwCache {
+  static constexpr int R = pick_radix(L / NS, E);
+  static constexpr int NB = E / R;
+  float2 w[NS > 1 ? NB * (R - 1) : 1];
+  TwCache<L, E, NS * R> next;
+  // ld(i) = exp(-2 pi i i / L), 0 <= i < L
+  template <typename Ld>
+  __device__ __forceinline__ void load(int tid, Ld ld) {
+    constexpr int T = L / E;
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int jm = (tid + b * T) % NS;
+#pragma unroll
+        for (int k = 1; k < R; ++k) w[b * (R - 1) + k - 1] = ld(k * jm * (L / (NS * R)));
+      }
+    }
+    next.load(tid, ld);
+  }
+};
+template <int L, int E, int NS>
+struct TwCache<L, E, NS, true> {
+  template <typename Ld>
+  __device__ __forceinline__ void load(int, Ld) {}
+};
+
+template <int L, int E, int NS, int STR, bool PAD, bool WAVE>
+struct FftPassesC {
+  static constexpr int R = pick_radix(L / NS, E);
+  __device__ __forceinline__ static void run(float2 (&v)[E], LdsView<STR, PAD> buf, int tid,
+                                             const TwCache<L, E, NS>& tc) {
+    stockham_pass_g<L, E, R, NS, STR, PAD, WAVE>(
+        v, buf, tid, [&](int b, int k, int) { return tc.w[NS > 1 ? b * (R - 1) + k - 1 : 0]; });
+    if constexpr (NS * R < L) FftPassesC<L, E, NS * R, STR, PAD, WAVE>::run(v, buf, tid, tc.next);
+  }
+};
+
+// Forward transform with the twiddles of a TwCache.
+template <int L, int E, int STR, bool PAD = false, bool WAVE = false>
+__device__ __forceinline__ void fft_forward_c(float2 (&v)[E], LdsView<STR, PAD> buf, int tid,
+                                              const TwCache<L, E>& tc) {
+  static_assert(L % E == 0, "E must divide L");
+  static_assert(fft_schedule_ok(L, E), "no radix schedule");
+  FftPassesC<L, E, 1, STR, PAD, WAVE>::run(v, buf, tid, tc);
+}
+
+// Inverse transform with the twiddles of a TwCache (conjugation trick).
+template <int L, int E, int STR, bool PAD = false, bool WAVE = false>
+__device__ __forceinline__ void fft_inverse_c(float2 (&v)[E], LdsView<STR, PAD> buf, int tid,
+                                              const TwCache<L, E>& tc) {
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = cconj(v[e]);
+  fft_forward_c<L, E, STR, PAD, WAVE>(v, buf, tid, tc);
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = cconj(v[e]);
 }
 
 // Inverse transform, exp(+2 pi i n k / L), unnormalised (conjugation trick).

@@ -30,9 +30,10 @@
 // T = L/E threads with E values each (E = 16 by default).  For L <= 1024 a wave vector lives
 // inside one wavefront, so after the cooperative load every wave runs on its
 // own (wave-local sync, shuffle reductions); longer transforms span waves and
-// synchronise the workgroup.  LDS per wave vector: the offset-free sequence
-// (later its prefix sums, as doubles) and one exchange buffer; per workgroup
-// the L-point twiddle table, read by every pass of all three transforms.  Global reads
+// synchronise the workgroup.  LDS per wave vector: the input sequence
+// (later its prefix sums, as doubles) and one exchange buffer.  The twiddles
+// of every FFT pass are fetched once per thread into registers and serve all
+// three transforms.  Global reads
 // use buffer loads (scalar base, 32-bit offsets; reads past the described
 // range return 0, which supplies the zero padding).
 #include <hip/hip_fp16.h>
@@ -118,13 +119,14 @@ __device__ __forceinline__ double group_excl_scan(double v, int tid, double* scr
 // for a slot that holds none; a null qmap means slot s holds wave vector s.
 // F16 (blocked store only): complex FP16 scaled by 2^qexp[q], unscaled on load
 // (exact: a power of two).
-template <int L, int QPW, int QB, int E, bool TWL, bool F16>
+template <int L, int QPW, int QB, int E, bool FULL, bool F16>
 __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__ spec, int64_t nq,
                                                        int N, int M, const float2* __restrict__ twN2,
                                                        const double* __restrict__ ramp,
                                                        const int32_t* __restrict__ qmap,
                                                        const int32_t* __restrict__ qexp,
                                                        float* __restrict__ D) {
+  // FULL: N == L and M == L (no padding, every lag), so no bounds tests.
   constexpr int T = L / E;
   constexpr bool WAVE = (T <= 64);
   constexpr int XS = lds_len<true>(L) + 1;  // staging stride (odd: spreads the transposed writes)
@@ -134,9 +136,7 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
   __shared__ float2 yall[QPW * YS];
   __shared__ double red[QPW * (T > 64 ? T / 64 : 1)];
   __shared__ float redf[QPW * (T > 64 ? T / 64 : 1)];
-  // L-point FFT twiddles exp(-2 pi i j / L), shared by the workgroup's
-  // transforms (TWL), else read from the global table at stride 2
-  __shared__ float2 twl[TWL ? L : 1];
+  if (FULL && (N != L || M != L)) return;  // guarded by the launcher; uniform
 
   // Workgroup -> first wave vector.  When a workgroup covers only part of a
   // layout block (QPW < QB), the QB/QPW workgroups that share the block's
@@ -152,13 +152,14 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
   }
   if (q0 >= nq) return;  // uniform for the whole workgroup
 
+  const int qi = threadIdx.x / T;
+  const int tid = threadIdx.x % T;
   const __amdgpu_buffer_rsrc_t tw_r = make_rsrc(twN2, 2u * L * sizeof(float2));
   const __amdgpu_buffer_rsrc_t ramp_r = make_rsrc(ramp, (uint32_t)N * sizeof(double));
-  if constexpr (TWL) {
-    for (int j = threadIdx.x; j < L; j += NT) twl[j] = ld_f2(tw_r, (uint32_t)(2 * j) * 8u);
-  }
-  const float2* ftw = TWL ? twl : twN2;
-  constexpr int ftws = TWL ? 1 : 2;
+  // twiddles of every FFT pass, exp(-2 pi i j / L) = twN2[2 j], held in
+  // registers and shared by the three transforms of the wave vector
+  TwCache<L, E> tc;
+  tc.load(tid, [&](int j) { return ld_f2(tw_r, (uint32_t)(2 * j) * 8u); });
 
   // ---- cooperative load of QPW time sequences into LDS, [q][t] ----
   {
@@ -187,7 +188,7 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
       uint32_t off;
       if constexpr (QB == 1) {
         const int i = f / L, t = f % L;
-        off = (t < N) ? (uint32_t)(i * N + t) * 8u : 0xFFFFFFF0u;
+        off = (FULL || t < N) ? (uint32_t)(i * N + t) * 8u : 0xFFFFFFF0u;
       } else {
         const int t = f / QPW, i = f % QPW;
         off = (uint32_t)(t * QB + i) * ES;
@@ -211,8 +212,6 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
   }
   __syncthreads();
 
-  const int qi = threadIdx.x / T;
-  const int tid = threadIdx.x % T;
   const int64_t q = q0 + qi;  // slot of this wave vector in the store
   const int qd = (q < nq) ? (qmap ? qmap[q] : (int)q) : -1;  // its row of D (-1: a hole)
   LdsView<1, true> xb{xall + qi * XS};
@@ -222,15 +221,14 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
   float* scratchf = redf + qi * (T > 64 ? T / 64 : 1);
 
   // ---- offset: FP32 mean over the contiguous chunk [tid*E, tid*E+E), fixed order ----
+  float mr, mi;
   {
-    float2 c[E];
-#pragma unroll
-    for (int i = 0; i < E; ++i) c[i] = xb[tid * E + i];
     float sr[E / 2], si[E / 2];
 #pragma unroll
     for (int i = 0; i < E / 2; ++i) {
-      sr[i] = c[2 * i].x + c[2 * i + 1].x;
-      si[i] = c[2 * i].y + c[2 * i + 1].y;
+      const float2 a = xb[tid * E + 2 * i], b = xb[tid * E + 2 * i + 1];
+      sr[i] = a.x + b.x;
+      si[i] = a.y + b.y;
     }
 #pragma unroll
     for (int w = E / 4; w > 0; w >>= 1)
@@ -240,48 +238,50 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
         si[i] += si[i + w];
       }
     const float inv_n = 1.0f / (float)N;
-    const float mr = group_sum<T>(sr[0], tid, scratchf) * inv_n;
-    const float mi = group_sum<T>(si[0], tid, scratchf) * inv_n;
-    // offset-free sequence x' (FP32), zero beyond N, written back in place
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int n = tid * E + i;
-      xb[n] = (n < N) ? make_float2(c[i].x - mr, c[i].y - mi) : make_float2(0.f, 0.f);
-    }
+    mr = group_sum<T>(sr[0], tid, scratchf) * inv_n;
+    mi = group_sum<T>(si[0], tid, scratchf) * inv_n;
   }
-  group_sync<WAVE>();
+  // offset-free sequence x' = x - mean for n < N, 0 beyond
+  auto xp = [&](float2 a, int n) {
+    return (FULL || n < N) ? make_float2(a.x - mr, a.y - mi) : make_float2(0.f, 0.f);
+  };
 
   // ---- X_odd = FFT_L(x' w^n), w = e^{-2 pi i / N2}; X_even = FFT_L(x') ----
   float2 v[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = cmul(xb[tid + e * T], ld_f2(tw_r, (uint32_t)(tid + e * T) * 8u));
-  fft_forward<L, E, 1, true, WAVE>(v, yb, tid, ftw, ftws);
+  for (int e = 0; e < E; ++e) {
+    const int n = tid + e * T;
+    v[e] = cmul(xp(xb[n], n), ld_f2(tw_r, (uint32_t)n * 8u));
+  }
+  fft_forward_c<L, E, 1, true, WAVE>(v, yb, tid, tc);
   float po[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) po[e] = v[e].x * v[e].x + v[e].y * v[e].y;
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = xb[tid + e * T];
-  fft_forward<L, E, 1, true, WAVE>(v, yb, tid, ftw, ftws);
+  for (int e = 0; e < E; ++e) v[e] = xp(xb[tid + e * T], tid + e * T);
+  fft_forward_c<L, E, 1, true, WAVE>(v, yb, tid, tc);
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = make_float2(v[e].x * v[e].x + v[e].y * v[e].y, po[e]);
 
   // ---- z = IFFT_L(P_even + i P_odd), unnormalised; v[e] = z[tid + e*T] ----
-  fft_inverse<L, E, 1, true, WAVE>(v, yb, tid, ftw, ftws);
+  fft_inverse_c<L, E, 1, true, WAVE>(v, yb, tid, tc);
 #pragma unroll
   for (int e = 0; e < E; ++e) yb[tid + e * T] = v[e];
 
-  // ---- prefix sums S(k) = sum_{j<k} |x'_j|^2, accumulated in FP64 ----
+  // ---- prefix sums S(k) = sum_{j<k} |x'_j|^2, accumulated in FP64 over the
+  // contiguous chunk [tid*E, tid*E+E) of this thread, then across threads ----
   {
     double s[E];
     double run = 0.0;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-      const float2 a = xb[tid * E + i];
+      const float2 a = xp(xb[tid * E + i], tid * E + i);
       s[i] = run;
       run += (double)(a.x * a.x + a.y * a.y);
     }
     double total;
     const double before = group_excl_scan<T>(run, tid, scratch, &total);
+    // each thread rewrites only the chunk it has just read
 #pragma unroll
     for (int i = 0; i < E; ++i) xd[LdsView<1, true>::slot(tid * E + i)] = before + s[i];
     // S(N) sits in slot L (one past the sequence) so that every lag reads the same way
@@ -297,7 +297,7 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int m = tid + e * T;
-      if (m < M) {
+      if (FULL || m < M) {
         const float2 zm = v[e];
         const float2 zr = yb[(L - m) & (L - 1)];
         const float2 w = ld_f2(tw_r, (uint32_t)m * 8u);  // (cos th, -sin th), th = 2 pi m / N2
@@ -351,9 +351,18 @@ TimeCfg time_cfg(int L) {
   return c;
 }
 
-static bool time_twl() {
-  static const char* env = std::getenv("DDM_TIME_TWL");
-  return env == nullptr || std::atoi(env) != 0;  // default on
+template <int L, int QPW, int QB, int E, bool FULL>
+static void time_launch(hipStream_t s, dim3 grid, dim3 block, const void* spec, int64_t nq, int N, int M,
+                        const float2* tw, const double* ramp, const int32_t* qmap, const int32_t* qexp, float* D) {
+  if constexpr (QB > 1) {
+    if (qexp != nullptr) {
+      hipLaunchKernelGGL((k_time<L, QPW, QB, E, FULL, true>), grid, block, 0, s, spec, nq, N, M, tw, ramp, qmap,
+                         qexp, D);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_time<L, QPW, QB, E, FULL, false>), grid, block, 0, s, spec, nq, N, M, tw, ramp, qmap,
+                     nullptr, D);
 }
 
 template <int L, int QPW, int QB, int E>
@@ -368,29 +377,10 @@ static hipError_t time_go(hipStream_t s, const void* spec, int64_t nq, int N, in
   }
   if (nwg == 0) return hipSuccess;
   const dim3 grid((unsigned)nwg), block(QPW * (L / E));
-  if constexpr (QPW * (2 * L + L / 8 + 1) * 8 + L * 8 <= 163840) {
-    if (time_twl()) {
-      if constexpr (QB > 1) {
-        if (qexp != nullptr) {
-          hipLaunchKernelGGL((k_time<L, QPW, QB, E, true, true>), grid, block, 0, s, spec, nq, N, M, tw, ramp,
-                             qmap, qexp, D);
-          return hipGetLastError();
-        }
-      }
-      hipLaunchKernelGGL((k_time<L, QPW, QB, E, true, false>), grid, block, 0, s, spec, nq, N, M, tw, ramp,
-                         qmap, nullptr, D);
-      return hipGetLastError();
-    }
-  }
-  if constexpr (QB > 1) {
-    if (qexp != nullptr) {
-      hipLaunchKernelGGL((k_time<L, QPW, QB, E, false, true>), grid, block, 0, s, spec, nq, N, M, tw, ramp,
-                         qmap, qexp, D);
-      return hipGetLastError();
-    }
-  }
-  hipLaunchKernelGGL((k_time<L, QPW, QB, E, false, false>), grid, block, 0, s, spec, nq, N, M, tw, ramp,
-                     qmap, nullptr, D);
+  if (N == L && M == L)
+    time_launch<L, QPW, QB, E, true>(s, grid, block, spec, nq, N, M, tw, ramp, qmap, qexp, D);
+  else
+    time_launch<L, QPW, QB, E, false>(s, grid, block, spec, nq, N, M, tw, ramp, qmap, qexp, D);
   return hipGetLastError();
 }
 
