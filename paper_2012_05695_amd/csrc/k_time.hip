@@ -48,6 +48,7 @@ namespace ddm {
 namespace {
 
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer descriptor, gfx9 family
+constexpr int kTailLags = 16;           // lags summed directly from the definition
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kRsrcWord3);
@@ -268,6 +269,32 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
 #pragma unroll
   for (int e = 0; e < E; ++e) yb[tid + e * T] = v[e];
 
+  // ---- the kTailLags largest lags, where D averages fewer than kTailLags
+  // pairs: Eq. (1) summed directly (FP32 differences of the raw sequence; a
+  // constant offset cancels).  The FFT route's rounding error in c(m) is
+  // spread evenly over the lags while D(m) divides by N - m, so it is largest
+  // exactly there.  Read before the prefix sums overwrite the sequence. ----
+  float dtail[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    dtail[e] = 0.0f;
+    const int m = tid + e * T;
+    // with N == L the candidates are the last e only (T >= kTailLags)
+    if ((!FULL || T < kTailLags || e == E - 1) && m >= N - kTailLags && m > 0 && m < M) {
+      // all kTailLags pairs at once (indices clamped into the sequence, the
+      // pairs past N dropped), summed in order
+      float acc = 0.0f;
+#pragma unroll
+      for (int j = 0; j < kTailLags; ++j) {
+        const float2 a = xb[min(m + j, N - 1)], b = xb[j];
+        const float dx = a.x - b.x, dy = a.y - b.y;
+        const float t = fmaf(dx, dx, dy * dy);
+        acc += (j < N - m) ? t : 0.0f;
+      }
+      dtail[e] = acc;
+    }
+  }
+
   // ---- prefix sums S(k) = sum_{j<k} |x'_j|^2, accumulated in FP64 over the
   // contiguous chunk [tid*E, tid*E+E) of this thread, then across threads ----
   {
@@ -305,7 +332,8 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
         const float two_c = 0.5f * ((zm.x + zr.x) + w.x * (zm.y + zr.y) - w.y * (zm.x - zr.x)) * inv_l;
         const double num = (xd[LdsView<1, true>::slot(N - m)] + sN) - xd[LdsView<1, true>::slot(m)] -
                            (double)two_c;
-        const double dm = num * ld_f64(ramp_r, (uint32_t)m * 8u);
+        const double sum = (m >= N - kTailLags) ? (double)dtail[e] : num;
+        const double dm = sum * ld_f64(ramp_r, (uint32_t)m * 8u);
         // lag 0 pairs every frame with itself: D(q, 0) = 0 exactly by definition
         drow[m] = (m == 0) ? 0.0f : (float)dm;
       }
