@@ -304,7 +304,8 @@ typedef enum ddm_kernel_kind {
   DDM_KERNEL_ROW = 1,    /* row transforms of step one */
   DDM_KERNEL_COL = 2,    /* column transforms + spectra write of step one */
   DDM_KERNEL_TIME = 4,   /* per-wave-vector time transform of step two */
-  DDM_KERNEL_RADIAL = 8  /* radial average */
+  DDM_KERNEL_RADIAL = 8, /* radial average */
+  DDM_KERNEL_STEP1 = 16  /* step one in one launch (rows and columns; square frames up to 512) */
 } ddm_kernel_kind;
 
 /* Bracket every launch of the kernel kinds in kernel_mask with a pair of HIP

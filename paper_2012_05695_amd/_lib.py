@@ -30,6 +30,7 @@ DDM_KERNEL_ROW = 1
 DDM_KERNEL_COL = 2
 DDM_KERNEL_TIME = 4
 DDM_KERNEL_RADIAL = 8
+DDM_KERNEL_STEP1 = 16
 
 DDM_PIX_U8 = 1
 DDM_PIX_U16 = 2

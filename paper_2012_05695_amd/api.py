@@ -158,7 +158,7 @@ class Plan:
 
     # -- profiling (event pairs around launches on the plan's stream) --
     KERNELS = {"row": L.DDM_KERNEL_ROW, "col": L.DDM_KERNEL_COL, "time": L.DDM_KERNEL_TIME,
-               "radial": L.DDM_KERNEL_RADIAL}
+               "radial": L.DDM_KERNEL_RADIAL, "step1": L.DDM_KERNEL_STEP1}
 
     def set_profiling(self, kinds=()):
         mask = 0

@@ -72,6 +72,13 @@ struct ddm_plan_s {
   std::vector<int32_t> qoff, kxcnt;
   int kx_needed, cw, kxw, ncol_tiles;
   int kxnyq;  // W/2 when the Nyquist column is kept (packed with kx = 0), else -1
+  // step one in one launch (square frames up to 512): workgroups, control
+  // slots, workspace frames it needs, and the error flag of the last launch
+  bool fused;
+  int s1_nwg, s1_maxslots, s1_frames;
+  int32_t* s1_err_host;  // pinned
+  hipEvent_t s1_ev;
+  bool s1_pending;
   size_t frame_inter_bytes;
   int fb_target;
   hipStream_t stream;
@@ -108,8 +115,8 @@ struct ddm_plan_s {
   uint32_t prof_mask;
   struct Rec { uint32_t kind; hipEvent_t a, b; };
   std::vector<Rec> prof_recs;
-  double prof_ms[4];
-  int64_t prof_n[4];
+  double prof_ms[5];
+  int64_t prof_n[5];
 };
 
 static int kind_slot(uint32_t kind) {
@@ -118,6 +125,7 @@ static int kind_slot(uint32_t kind) {
     case DDM_KERNEL_COL: return 1;
     case DDM_KERNEL_TIME: return 2;
     case DDM_KERNEL_RADIAL: return 3;
+    case DDM_KERNEL_STEP1: return 4;
     default: return -1;
   }
 }
@@ -266,6 +274,20 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
   p->kxw = p->ncol_tiles * p->cw;
   p->frame_inter_bytes = (size_t)H * p->kxw * sizeof(float2);
   p->fb_target = (int)std::max<size_t>(1, std::min<size_t>(N, kInterTargetBytes / p->frame_inter_bytes));
+  // Step one in one launch where it applies (DDM_STEP1=split keeps the two
+  // kernels): its intermediates (step1_bufs() frames per XCD) and control words
+  // take the place of the batch of intermediates.
+  p->fused = step1_fusable(W, H, p->ncol_tiles, p->kxw);
+  if (const char* v = std::getenv("DDM_STEP1")) p->fused = p->fused && std::strcmp(v, "split") != 0;
+  p->s1_nwg = p->s1_maxslots = p->s1_frames = 0;
+  if (p->fused) {
+    const int ipf = H / 32 + p->ncol_tiles;  // row items (32 rows each) + column items per frame
+    p->s1_nwg = step1_workgroups(W);
+    p->s1_maxslots = N + p->s1_nwg / ipf + 4;
+    const size_t ctl_bytes = step1_ctl_words(p->s1_maxslots) * sizeof(int32_t);
+    p->s1_frames = 8 * step1_bufs() + (int)((ctl_bytes + p->frame_inter_bytes - 1) / p->frame_inter_bytes);
+    p->fb_target = p->s1_frames;
+  }
   // Slots of the blocked store: the kept kx < KR of row ky fill slots
   // sbase[ky] + kx, each row rounded up to whole blocks, so that a column tile
   // of 16 writes whole 128-byte lines; packed Nyquist values (ky, W/2) follow
@@ -342,7 +364,7 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
   p->ws = nullptr;
   p->ws_bytes = 0;
   p->prof_mask = 0;
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < 5; ++i) {
     p->prof_ms[i] = 0.0;
     p->prof_n[i] = 0;
   }
@@ -365,6 +387,21 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
     }
     *p->sat_host = 0;
   }
+  p->s1_err_host = nullptr;
+  p->s1_ev = nullptr;
+  p->s1_pending = false;
+  if (p->fused) {
+    if ((e = hipHostMalloc((void**)&p->s1_err_host, sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&p->s1_ev, hipEventDisableTiming)) != hipSuccess) {
+      if (p->s1_err_host) hipHostFree(p->s1_err_host);
+      if (p->sat_ev) hipEventDestroy(p->sat_ev);
+      if (p->sat_host) hipHostFree(p->sat_host);
+      hipFree(p->dev_tables);
+      delete p;
+      return hip_fail(e, "step one flag setup");
+    }
+    *p->s1_err_host = 0;
+  }
   *out = p;
   g_err.clear();
   return DDM_OK;
@@ -377,6 +414,8 @@ ddm_status ddm_plan_destroy(ddm_plan_t p) {
   prof_drain(p);
   if (p->sat_ev) hipEventDestroy(p->sat_ev);
   if (p->sat_host) hipHostFree(p->sat_host);
+  if (p->s1_ev) hipEventDestroy(p->s1_ev);
+  if (p->s1_err_host) hipHostFree(p->s1_err_host);
   p->magic = 0;
   if (p->dev_tables) hipFree(p->dev_tables);
   if (p->thr_d) hipFree(p->thr_d);
@@ -475,6 +514,27 @@ static ddm_status run_step_one(ddm_plan_s* p, const void* frames, float2* inter,
                                int64_t s_hi, int qb, SpecOut out) {
   QTable qt{p->qoff_d, p->kxcnt_d};
   const SlotMap sm = (qb == 1) ? SlotMap{p->qoff_d, -1} : SlotMap{p->sbase_d, p->sN};
+  if (p->fused && qb == kSpecQB && fb >= p->s1_frames) {
+    int* ctl = (int*)(inter + (size_t)8 * step1_bufs() * ((size_t)p->H * p->kxw));
+    hipError_t e;
+    {
+      ProfScope ps(p, DDM_KERNEL_STEP1);
+      e = launch_step1(p->stream, p->d.pixel, frames, p->W, p->N, p->d.precondition, inter, p->kxw, p->ncol_tiles,
+                       p->kxnyq, qt, sm, s_lo, s_hi, out, p->twW, p->twH, ctl, p->s1_maxslots, p->s1_nwg);
+    }
+    if (e != hipSuccess) return hip_fail(e, "step one launch");
+    // the wait-ran-out flag comes back with the next call (not from inside a graph capture)
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    e = hipStreamIsCapturing(p->stream, &cs);
+    if (e == hipSuccess && cs == hipStreamCaptureStatusNone) {
+      e = hipMemcpyAsync(p->s1_err_host, ctl + step1_ctl_words(p->s1_maxslots) - 1, sizeof(int32_t),
+                         hipMemcpyDeviceToHost, p->stream);
+      if (e == hipSuccess) e = hipEventRecord(p->s1_ev, p->stream);
+      if (e == hipSuccess) p->s1_pending = true;
+    }
+    if (e != hipSuccess) return hip_fail(e, "step one flag copy");
+    return DDM_OK;
+  }
   for (int t0 = 0; t0 < p->N; t0 += fb) {
     const int nf = std::min(fb, p->N - t0);
     hipError_t e;
@@ -515,6 +575,19 @@ static ddm_status run_pilot(ddm_plan_s* p, const void* frames, float2* inter, fl
 }
 
 // Fold a finished saturation count into the plan's sticky total.
+// Result of the last fused step one: DDM_ERR_HIP if one of its waits ran out.
+static ddm_status s1_collect(ddm_plan_s* p) {
+  if (!p->s1_pending) return DDM_OK;
+  hipError_t e = hipEventSynchronize(p->s1_ev);
+  if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  p->s1_pending = false;
+  if (*p->s1_err_host != 0) {
+    *p->s1_err_host = 0;
+    return fail(DDM_ERR_HIP, "step one: a wait between its row and column work ran out; the result of the previous call is not valid");
+  }
+  return DDM_OK;
+}
+
 static hipError_t sat_collect(ddm_plan_s* p) {
   if (!p->sat_pending) return hipSuccess;
   hipError_t e = hipEventSynchronize(p->sat_ev);
@@ -530,6 +603,8 @@ ddm_status ddm_structure_function(ddm_plan_t p, const void* frames, float* D) {
   if (frames == nullptr || D == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "frames/D is NULL");
   if (((uintptr_t)frames & 15) != 0) return fail(DDM_ERR_INVALID_ARGUMENT, "frames must be 16-byte aligned");
   if (p->ws == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "no workspace attached (ddm_plan_set_workspace)");
+  st = s1_collect(p);
+  if (st != DDM_OK) return st;
   hipError_t e = sat_collect(p);
   if (e != hipSuccess) return hip_fail(e, "saturation count");
   int fb;
@@ -662,10 +737,10 @@ ddm_status ddm_radial_average(ddm_plan_t p, const float* D, const int64_t* thr, 
 ddm_status ddm_plan_set_profiling(ddm_plan_t p, uint32_t mask) {
   ddm_status st = check_plan(p);
   if (st != DDM_OK) return st;
-  if (mask & ~15u) return fail(DDM_ERR_INVALID_ARGUMENT, "unknown kernel kind bits in mask 0x%x", mask);
+  if (mask & ~31u) return fail(DDM_ERR_INVALID_ARGUMENT, "unknown kernel kind bits in mask 0x%x", mask);
   hipError_t e = prof_drain(p);
   p->prof_mask = mask;
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < 5; ++i) {
     p->prof_ms[i] = 0.0;
     p->prof_n[i] = 0;
   }

@@ -19,10 +19,14 @@
 //          B_k = (C_k - conj C_{-k})/(2i).
 #include <hip/hip_fp16.h>
 
+#include <algorithm>
+
 #include "fft.hpp"
 #include "internal.hpp"
 
 namespace ddm {
+
+typedef unsigned int v2u32 __attribute__((ext_vector_type(2)));
 
 // Eight pixels of one row, loaded at once (16 bytes of uint16, 8 of uint8).
 template <typename PIX> struct Pix8;
@@ -43,34 +47,51 @@ template <> struct Pix8<uint8_t> {
   __device__ __forceinline__ static vec zero() { return make_uint2(0u, 0u); }
 };
 
-template <int W, int E, typename PIX>
-__global__ void __launch_bounds__(256) k_row(const PIX* __restrict__ frames, int H, int t0,
-                                             int precondition, float2* __restrict__ inter, int kxw,
-                                             int pack, const float2* __restrict__ tw, int tws) {
+// Row item: rows [ybase, ybase + 2 nt) of frame t (nt row pairs, one per T
+// threads; the caller's block holds nt * T threads) -> out rows [2 nt][kxw],
+// out = the intermediate at row ybase.  lds: nt * lds_len(W) complex values.
+// Non-temporal loads of the 8-pixel chunks (through native vector types).
+__device__ __forceinline__ uint4 nt_load(const uint4* p) {
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  const u4 x = __builtin_nontemporal_load(reinterpret_cast<const u4*>(p));
+  return make_uint4(x[0], x[1], x[2], x[3]);
+}
+__device__ __forceinline__ uint2 nt_load(const uint2* p) {
+  const v2u32 x = __builtin_nontemporal_load(reinterpret_cast<const v2u32*>(p));
+  return make_uint2(x[0], x[1]);
+}
+
+template <int W, int E, typename PIX, bool DEV = false, bool NT = false>
+__device__ __forceinline__ void row_item(const PIX* __restrict__ frames, int H, int t, int ybase, int nt,
+                                         int precondition, float2* __restrict__ out, int kxw, int pack,
+                                         const float2* __restrict__ tw, int tws, float2* lds_row, int tx) {
   constexpr int T = W / E;
   constexpr bool WAVE = (T <= 64) && (64 % T == 0);  // a transform inside one wavefront
   constexpr int WL = lds_len<true>(W);
   constexpr int CPR = W / 8;  // 8-pixel chunks per row
   using P8 = Pix8<PIX>;
   using vec = typename P8::vec;
-  extern __shared__ float2 lds_row[];
-  const int p = threadIdx.x / T;  // transform (row pair) within the workgroup
-  const int tid = threadIdx.x % T;
-  const int nt = blockDim.x / T;
-  const int ybase = blockIdx.x * nt * 2;
-  const int t = t0 + blockIdx.y;
+  const int p = tx / T;  // transform (row pair) within the block (tx = thread index)
+  const int tid = tx % T;
+  const int nthr = nt * T;
 
-  // Stage the rows of the block: chunk g = 8 pixels of rows 2p', 2p'+1 (minus
-  // frame 0), written as 8 consecutive complex values of transform p' (inside
-  // one padding group, so one contiguous 64-byte run).
+  // Stage the rows: chunk g = 8 pixels of rows 2p', 2p'+1 (minus frame 0),
+  // written as 8 consecutive complex values of transform p' (inside one
+  // padding group, so one contiguous 64-byte run).
   {
     const PIX* src = frames + ((size_t)t * H + ybase) * W;
     const PIX* ref = frames + (size_t)ybase * W;
-    for (int g = threadIdx.x; g < nt * CPR; g += blockDim.x) {
+    for (int g = tx; g < nt * CPR; g += nthr) {
       const int pp = g / CPR, n0 = (g % CPR) * 8;
       const int off = 2 * pp * W + n0;
-      const vec a0 = *reinterpret_cast<const vec*>(src + off);
-      const vec a1 = *reinterpret_cast<const vec*>(src + off + W);
+      vec a0, a1;
+      if constexpr (NT) {  // frames are read once: stream them past the L2
+        a0 = nt_load(reinterpret_cast<const vec*>(src + off));
+        a1 = nt_load(reinterpret_cast<const vec*>(src + off + W));
+      } else {
+        a0 = *reinterpret_cast<const vec*>(src + off);
+        a1 = *reinterpret_cast<const vec*>(src + off + W);
+      }
       vec b0 = P8::zero(), b1 = P8::zero();
       if (precondition) {
         b0 = *reinterpret_cast<const vec*>(ref + off);
@@ -93,9 +114,18 @@ __global__ void __launch_bounds__(256) k_row(const PIX* __restrict__ frames, int
 #pragma unroll
   for (int e = 0; e < E; ++e) buf[tid + e * T] = v[e];
   group_sync<WAVE>();
-  const int y0 = ybase + 2 * p;
-  float2* o0 = inter + ((size_t)blockIdx.y * H + y0) * kxw;
+  float2* o0 = out + (size_t)(2 * p) * kxw;
   float2* o1 = o0 + kxw;
+  // DEV: device-scope stores (written through to memory), for rows that other
+  // workgroups of the same launch read back
+  auto put = [&](float2* o, int k, float2 val) {
+    if constexpr (DEV) {
+      const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(o, (short)0, kxw * 8, 0x00020000);
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u32, val), r, (uint32_t)k * 8u, 0, 0x10);
+    } else {
+      o[k] = val;
+    }
+  };
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int k = tid + e * T;
@@ -104,21 +134,33 @@ __global__ void __launch_bounds__(256) k_row(const PIX* __restrict__ frames, int
       const float2 zm = buf[k == 0 ? 0 : W - k];
       if (k == 0 && pack) {
         const float2 zn = buf[W / 2];  // Z_{W/2}: R_y(W/2) = Re, R_{y+1}(W/2) = Im
-        o0[0] = make_float2(zk.x, zn.x);
-        o1[0] = make_float2(zk.y, zn.y);
+        put(o0, 0, make_float2(zk.x, zn.x));
+        put(o1, 0, make_float2(zk.y, zn.y));
       } else {
-        o0[k] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-        o1[k] = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+        put(o0, k, make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)));
+        put(o1, k, make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x)));
       }
     }
   }
+}
+
+template <int W, int E, typename PIX>
+__global__ void __launch_bounds__(256) k_row(const PIX* __restrict__ frames, int H, int t0,
+                                             int precondition, float2* __restrict__ inter, int kxw,
+                                             int pack, const float2* __restrict__ tw, int tws) {
+  extern __shared__ float2 lds_row[];
+  const int nt = blockDim.x / (W / E);
+  const int ybase = blockIdx.x * nt * 2;
+  row_item<W, E, PIX>(frames, H, t0 + blockIdx.y, ybase, nt, precondition,
+                      inter + ((size_t)blockIdx.y * H + ybase) * kxw, kxw, pack, tw, tws, lds_row, threadIdx.x);
 }
 
 // One value of the column transform into the spectra store: slot sl (group-
 // local index j = sl - s_lo), time t, at [j / QB][N][QB].  F16: complex FP16
 // scaled by 2^qexp[q] (round to nearest even), |value| > 65504 clamped and
 // counted.
-template <int QB, bool F16>
+// NT: non-temporal stores (streamed past the L2 without displacing what it holds).
+template <int QB, bool F16, bool NT = false>
 __device__ __forceinline__ void put_spec(void* __restrict__ spec, int sl, int s_lo, int s_hi, int N, int t,
                                          float2 val, int q, const int32_t* __restrict__ qexp, int& nsat) {
   if (sl < s_lo || sl >= s_hi) return;
@@ -130,9 +172,18 @@ __device__ __forceinline__ void put_spec(void* __restrict__ spec, int sl, int s_
     const float lim = 65504.0f;
     if (!(fabsf(re) <= lim)) { re = copysignf(lim, re); ++nsat; }
     if (!(fabsf(im) <= lim)) { im = copysignf(lim, im); ++nsat; }
-    reinterpret_cast<__half2*>(spec)[at] = __halves2half2(__float2half_rn(re), __float2half_rn(im));
+    const __half2 h = __halves2half2(__float2half_rn(re), __float2half_rn(im));
+    if constexpr (NT)
+      __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, h), reinterpret_cast<uint32_t*>(spec) + at);
+    else
+      reinterpret_cast<__half2*>(spec)[at] = h;
   } else {
-    reinterpret_cast<float2*>(spec)[at] = val;
+    if constexpr (NT) {
+      __builtin_nontemporal_store(val.x, reinterpret_cast<float*>(spec) + 2 * at);
+      __builtin_nontemporal_store(val.y, reinterpret_cast<float*>(spec) + 2 * at + 1);
+    } else {
+      reinterpret_cast<float2*>(spec)[at] = val;
+    }
   }
 }
 
@@ -141,25 +192,41 @@ __device__ __forceinline__ void put_spec(void* __restrict__ spec, int sl, int s_
 // in slot sN + ky, or sbase[ky] + W/2 when sN < 0.  kxnyq = W/2 when column 0
 // of the intermediate carries R(0) + i R(W/2) (columns >= W/2 are then
 // padding), else -1.  qoff[ky] + kx is the wave vector (FP16 scale index).
-template <int H, int E, int CW, int QB, bool F16>
-__global__ void __launch_bounds__(CW * (H / E)) k_col(const float2* __restrict__ inter, int kxw, int t0,
-                                                      int N, const int32_t* __restrict__ qoff,
-                                                      const int32_t* __restrict__ kxcnt,
-                                                      const int32_t* __restrict__ sbase, int sN, int s_lo,
-                                                      int s_hi, int kxnyq, void* __restrict__ spec,
-                                                      const int32_t* __restrict__ qexp, int32_t* sat,
-                                                      const float2* __restrict__ tw, int tws) {
+// Column item, in two parts.  col_load: this thread's E values of column
+// kx of one frame's intermediate (BYPASS: reads that skip the CU's L1, for
+// data written by other workgroups during the same launch).
+template <int H, int E, int CW, bool BYPASS>
+__device__ __forceinline__ void col_load(float2 (&v)[E], const float2* __restrict__ frame_inter, int kxw, int kx,
+                                         int tid) {
   constexpr int T = H / E;
-  extern __shared__ float2 lds_col[];
-  const int c = threadIdx.x % CW;
-  const int tid = threadIdx.x / CW;
-  const int kx = blockIdx.x * CW + c;
-  const int t = t0 + blockIdx.y;
-  const float2* src = inter + (size_t)blockIdx.y * H * kxw + kx;
-  float2 v[E];
+  if constexpr (BYPASS) {
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float2*>(frame_inter), (short)0, (int)((size_t)H * kxw * sizeof(float2)), 0x00020000);
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = src[(size_t)(tid + e * T) * kxw];
-  // row tables of this thread's rows, fetched while the transform runs
+    for (int e = 0; e < E; ++e)
+      v[e] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(
+                                            r, (uint32_t)(((tid + e * T) * kxw + kx) * 8), 0, 0x10 /* sc1 */));
+  } else {
+    const float2* src = frame_inter + kx;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = src[(size_t)(tid + e * T) * kxw];
+  }
+}
+
+// col_fft_store: FFT of the loaded column tile (column c of CW), then the
+// kept values into the spectra store at time t.
+template <int H, int E, int CW, int QB, bool F16, bool NT = false>
+__device__ __forceinline__ void col_fft_store(float2 (&v)[E], int tile, int t, int N,
+                                              const int32_t* __restrict__ qoff, const int32_t* __restrict__ kxcnt,
+                                              const int32_t* __restrict__ sbase, int sN, int s_lo, int s_hi,
+                                              int kxnyq, void* __restrict__ spec, const int32_t* __restrict__ qexp,
+                                              int& nsat, const float2* __restrict__ tw, int tws, float2* lds_col,
+                                              int tx) {
+  constexpr int T = H / E;
+  const int c = tx % CW;
+  const int tid = tx / CW;
+  const int kx = tile * CW + c;
+  // row tables of this thread's rows
   int rs[E], rc[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -168,13 +235,12 @@ __global__ void __launch_bounds__(CW * (H / E)) k_col(const float2* __restrict__
   }
   LdsView<CW> buf{lds_col + c};
   fft_forward<H, E, CW>(v, buf, tid, tw, tws);
-  int nsat = 0;
   const int kxlim = kxnyq > 0 ? kxnyq : 0x7FFFFFFF;  // packing: columns >= W/2 are padding
-  const bool packed0 = kxnyq > 0 && blockIdx.x == 0;  // uniform over the workgroup
+  const bool packed0 = kxnyq > 0 && tile == 0;        // uniform over the workgroup
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     if (kx < rc[e] && kx < kxlim && !(packed0 && kx == 0))
-      put_spec<QB, F16>(spec, rs[e] + kx, s_lo, s_hi, N, t, v[e], F16 ? qoff[tid + e * T] + kx : 0, qexp, nsat);
+      put_spec<QB, F16, NT>(spec, rs[e] + kx, s_lo, s_hi, N, t, v[e], F16 ? qoff[tid + e * T] + kx : 0, qexp, nsat);
   }
   if (packed0) {
     // column 0 = FFT(R(0) + i R(W/2)): separate through LDS (every thread is
@@ -192,12 +258,197 @@ __global__ void __launch_bounds__(CW * (H / E)) k_col(const float2* __restrict__
         const float2 a = v[e], b = buf[ky == 0 ? 0 : H - ky];
         const int q0 = F16 ? qoff[ky] : 0;
         if (0 < rc[e])
-          put_spec<QB, F16>(spec, rs[e], s_lo, s_hi, N, t,
+          put_spec<QB, F16, NT>(spec, rs[e], s_lo, s_hi, N, t,
                             make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y)), q0, qexp, nsat);
         if (kxnyq < rc[e])
-          put_spec<QB, F16>(spec, sN >= 0 ? sN + ky : rs[e] + kxnyq, s_lo, s_hi, N, t,
+          put_spec<QB, F16, NT>(spec, sN >= 0 ? sN + ky : rs[e] + kxnyq, s_lo, s_hi, N, t,
                             make_float2(0.5f * (a.y + b.y), -0.5f * (a.x - b.x)), q0 + kxnyq, qexp, nsat);
       }
+    }
+  }
+}
+
+template <int H, int E, int CW, int QB, bool F16>
+__global__ void __launch_bounds__(CW * (H / E)) k_col(const float2* __restrict__ inter, int kxw, int t0,
+                                                      int N, const int32_t* __restrict__ qoff,
+                                                      const int32_t* __restrict__ kxcnt,
+                                                      const int32_t* __restrict__ sbase, int sN, int s_lo,
+                                                      int s_hi, int kxnyq, void* __restrict__ spec,
+                                                      const int32_t* __restrict__ qexp, int32_t* sat,
+                                                      const float2* __restrict__ tw, int tws) {
+  extern __shared__ float2 lds_col[];
+  float2 v[E];
+  col_load<H, E, CW, false>(v, inter + (size_t)blockIdx.y * H * kxw, kxw, blockIdx.x * CW + threadIdx.x % CW,
+                            threadIdx.x / CW);
+  int nsat = 0;
+  col_fft_store<H, E, CW, QB, F16>(v, blockIdx.x, t0 + blockIdx.y, N, qoff, kxcnt, sbase, sN, s_lo, s_hi, kxnyq,
+                                   spec, qexp, nsat, tw, tws, lds_col, threadIdx.x);
+  if (F16 && nsat > 0) atomicAdd(sat, nsat);
+}
+
+// ---------------------------------------------------------------------------
+// Step one in one persistent launch, for square frames whose row intermediate
+// fits an XCD's L2 (W = H <= 512).  Each XCD runs its own ordered stream of
+// items: step s holds the NR row items of slot s (a frame claimed from a global
+// counter) and then the NC column items of slot s - 1, so that column items
+// find their rows done instead of waiting for them.  Row items write the frame's intermediate into one
+// of kStep1Bufs buffers of that XCD; column items read it back from the XCD's
+// L2 (loads that skip L1) and write the spectra store.  A workgroup takes the
+// next ticket of its XCD and waits only for items with lower tickets of the
+// same XCD (column items: the slot's rows; row items: the columns of the slot
+// that last used the buffer; a slot's frame claim: the previous slot's claim),
+// so every wait ends whatever the residency; each
+// wait is also bounded, and a wait that runs out sets *err (reported by the
+// host) instead of hanging.  Control words per XCD: ticket, then per slot the
+// claimed frame (kUnset until published), rows done and columns done.
+// ---------------------------------------------------------------------------
+#ifndef S1_DEV_STORES
+#define S1_DEV_STORES false
+#endif
+constexpr int kStep1Bufs = 3;
+constexpr int kUnset = -2;
+// bound of one wait, in ticks of the 100 MHz constant clock (0.2 s)
+constexpr uint64_t kWaitTicks = 20000000ull;
+
+// Every access to the control words is an atomic read-modify-write (a poll
+// adds 0), so that writers and pollers meet at the same point of the memory
+// system; a poll that bypassed the cache while the update sat in the XCD's L2
+// would never see it.
+// (the zero is opaque to the compiler, which would otherwise turn the add of 0
+// into a plain load)
+__device__ __forceinline__ int ctl_read(int* p) {
+  int zero = 0;
+  asm volatile("" : "+v"(zero));
+  return atomicAdd(p, zero);
+}
+
+// Wait for *p != kUnset (returns it), or *p >= target; -1 / false once the
+// error flag is set, by this wait running out or by any other.
+__device__ __forceinline__ int spin_value(int* p, int* err) {
+  const uint64_t t0 = wall_clock64();
+  for (;;) {
+    const int v = ctl_read(p);
+    if (v != kUnset) return v;
+    if (ctl_read(err) != 0) return -1;
+    if (wall_clock64() - t0 > kWaitTicks) {
+      atomicExch(err, 1);
+      return -1;
+    }
+    __builtin_amdgcn_s_sleep(4);
+  }
+}
+
+__device__ __forceinline__ bool spin_ge(int* p, int target, int* err) {
+  const uint64_t t0 = wall_clock64();
+  for (;;) {
+    if (ctl_read(p) >= target) return true;
+    if (ctl_read(err) != 0) return false;
+    if (wall_clock64() - t0 > kWaitTicks) {
+      atomicExch(err, 1);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(4);
+  }
+}
+
+template <int W, int E, typename PIX, bool F16>
+__global__ void __launch_bounds__(16 * (W / E)) k_step1(const PIX* __restrict__ frames, int N, int precondition,
+                                                         float2* __restrict__ bufs, int kxw, int ncol_tiles,
+                                                         int pack, int kxnyq, const int32_t* __restrict__ qoff,
+                                                         const int32_t* __restrict__ kxcnt,
+                                                         const int32_t* __restrict__ sbase, int sN, int s_lo,
+                                                         int s_hi, void* __restrict__ spec,
+                                                         const int32_t* __restrict__ qexp, int32_t* sat,
+                                                         const float2* __restrict__ twW,
+                                                         const float2* __restrict__ twH, int* __restrict__ ctl,
+                                                         int maxslots) {
+  constexpr int H = W;
+  constexpr int T = W / E;
+  constexpr int CW = 16;
+  constexpr int NTR = CW;  // row pairs per row item: the block has CW * T threads
+  constexpr int NR = H / (2 * NTR);
+  extern __shared__ float2 lds[];
+  __shared__ int s_val, s_val2;
+  const int NC = ncol_tiles;
+  const int IPF = NR + NC;
+  const size_t frame_elems = (size_t)H * kxw;
+  // the XCD this wave runs on: hardware register XCC_ID (id 20), bits 3:0
+  const int xcc = (int)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7;
+  int* mine = ctl + (size_t)xcc * (1 + 3 * maxslots);
+  int* ticket = mine;
+  int* fidx = mine + 1;
+  int* rows = fidx + maxslots;
+  int* cols = rows + maxslots;
+  int* gframe = ctl + (size_t)8 * (1 + 3 * maxslots);
+  int* err = gframe + 1;
+  int nsat = 0;
+  for (;;) {
+    // ticket -> step s, position r: the row items of slot s, then the column
+    // items of slot s - 1 (whose rows finished a step earlier)
+    if (threadIdx.x == 0) s_val = atomicAdd(ticket, 1);
+    __syncthreads();
+    const int tk = s_val;
+    __syncthreads();
+    const int st = tk / IPF, r = tk % IPF;
+    if (st + 1 >= maxslots) break;  // uniform
+    if (threadIdx.x == 0) {
+      if (r == 0) {
+        // claims are in slot order per XCD: a slot claims a frame only after
+        // the previous slot (a lower ticket) got one, so once a slot is left
+        // without a frame every later slot is too
+        int f = -1;
+        const int prev = (st == 0) ? 0 : spin_value(&fidx[st - 1], err);
+        if (prev >= 0) {
+          f = atomicAdd(gframe, 1);
+          if (f >= N) f = -1;
+        }
+        atomicExch(&fidx[st], f);
+      }
+      const int fs = spin_value(&fidx[st], err);
+      const int fp = (st == 0) ? -1 : spin_value(&fidx[st - 1], err);
+      s_val = fs;
+      s_val2 = fp;
+    }
+    __syncthreads();
+    const int fs = s_val, fp = s_val2;
+    __syncthreads();
+    if (fs < 0 && fp < 0) break;  // uniform: nothing left in this step or after it
+    const bool is_row = r < NR;
+    const int k = is_row ? st : st - 1;  // the slot this item works on
+    const int f = is_row ? fs : fp;
+    if (f < 0) continue;  // uniform: this item's slot has no frame
+    float2* buf = bufs + (size_t)(xcc * kStep1Bufs + k % kStep1Bufs) * frame_elems;
+    // the thread index, made opaque per item so that the per-thread addresses
+    // of both item kinds are not hoisted out of the loop (they would all stay
+    // live in registers)
+    int tx = threadIdx.x;
+    asm volatile("" : "+v"(tx));
+    if (is_row) {
+      // the buffer is free once the columns of the slot that last used it
+      // have read it (that slot has a frame: claims are in slot order)
+      if (threadIdx.x == 0) s_val = (k < kStep1Bufs || spin_ge(&cols[k - kStep1Bufs], NC, err)) ? 1 : 0;
+      __syncthreads();
+      if (s_val == 0) break;  // uniform: a wait ran out
+      const int ybase = r * 2 * NTR;
+      row_item<W, E, PIX, S1_DEV_STORES, true>(frames, H, f, ybase, NTR, precondition, buf + (size_t)ybase * kxw,
+                                               kxw, pack, twW, 1, lds, tx);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the rows have reached L2
+      __syncthreads();
+      if (threadIdx.x == 0) atomicAdd(&rows[k], 1);
+    } else {
+      const int tile = r - NR;
+      if (threadIdx.x == 0) s_val = spin_ge(&rows[k], NR, err) ? 1 : 0;
+      __syncthreads();
+      if (s_val == 0) break;  // uniform: a wait ran out
+      // device-scope loads: this CU's L1 may still hold lines of the buffer
+      // from the slot that used it before
+      float2 v[E];
+      col_load<H, E, CW, true>(v, buf, kxw, tile * CW + tx % CW, tx / CW);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the tile is in registers
+      __syncthreads();
+      if (threadIdx.x == 0) atomicAdd(&cols[k], 1);
+      col_fft_store<H, E, CW, kSpecQB, F16, true>(v, tile, f, N, qoff, kxcnt, sbase, sN, s_lo, s_hi, kxnyq, spec,
+                                                  qexp, nsat, twH, 1, lds, tx);
     }
   }
   if (F16 && nsat > 0) atomicAdd(sat, nsat);
@@ -338,6 +589,73 @@ hipError_t launch_col(hipStream_t s, const float2* inter, int H, int kxw, int nt
     default:
       return hipErrorInvalidValue;
   }
+}
+
+// ---- fused step one ----
+__host__ __device__ size_t step1_ctl_words(int maxslots) { return (size_t)8 * (1 + 3 * (size_t)maxslots) + 2; }
+
+int step1_bufs() { return kStep1Bufs; }
+
+bool step1_fusable(int W, int H, int ncol_tiles, int kxw) {
+  if (W != H || kxw != 16 * ncol_tiles) return false;
+  return W == 64 || W == 128 || W == 256 || W == 512;
+}
+
+// control words: per XCD [ticket, fidx[maxslots] = kUnset, rows[maxslots], cols[maxslots]], then
+// the global frame counter and the error flag, all 0 except fidx
+__global__ void k_step1_init(int* ctl, int maxslots) {
+  const int64_t total = (int64_t)step1_ctl_words(maxslots);
+  const int64_t per = 1 + 3 * (int64_t)maxslots;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = i % per;
+    ctl[i] = (i < 8 * per && o >= 1 && o <= maxslots) ? kUnset : 0;
+  }
+}
+
+template <int W, typename PIX>
+static hipError_t step1_go(hipStream_t s, const void* frames, int N, int pre, float2* bufs, int kxw, int ntiles,
+                           int pack, int kxnyq, QTable qt, SlotMap sm, int s_lo, int s_hi, SpecOut out,
+                           const float2* twW, const float2* twH, int* ctl, int maxslots, int nwg) {
+  constexpr int E = 16, T = W / E, CW = 16;
+  const size_t lds = std::max((size_t)CW * lds_len<true>(W) * sizeof(float2), (size_t)CW * W * sizeof(float2));
+  if (out.qexp != nullptr)
+    hipLaunchKernelGGL((k_step1<W, E, PIX, true>), dim3(nwg), dim3(CW * T), lds, s, (const PIX*)frames, N, pre,
+                       bufs, kxw, ntiles, pack, kxnyq, qt.qoff, qt.kxcnt, sm.sbase, sm.sN, s_lo, s_hi, out.spec,
+                       out.qexp, out.sat, twW, twH, ctl, maxslots);
+  else
+    hipLaunchKernelGGL((k_step1<W, E, PIX, false>), dim3(nwg), dim3(CW * T), lds, s, (const PIX*)frames, N, pre,
+                       bufs, kxw, ntiles, pack, kxnyq, qt.qoff, qt.kxcnt, sm.sbase, sm.sN, s_lo, s_hi, out.spec,
+                       nullptr, nullptr, twW, twH, ctl, maxslots);
+  return hipGetLastError();
+}
+
+int step1_workgroups(int W) {
+  const size_t lds = std::max((size_t)16 * lds_len<true>(W) * sizeof(float2), (size_t)16 * W * sizeof(float2));
+  const int per_cu = (int)std::min<size_t>(8, (160 * 1024) / lds);
+  return 256 * std::max(1, per_cu);
+}
+
+hipError_t launch_step1(hipStream_t s, int pixel, const void* frames, int W, int N, int precondition,
+                        float2* bufs, int kxw, int ntiles, int kxnyq, QTable qt, SlotMap sm, int64_t s_lo,
+                        int64_t s_hi, SpecOut out, const float2* twW, const float2* twH, int* ctl, int maxslots,
+                        int nwg) {
+  hipLaunchKernelGGL(k_step1_init, dim3(64), dim3(256), 0, s, ctl, maxslots);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int pack = kxnyq > 0, lo = (int)s_lo, hi = (int)s_hi;
+#define S1_CASE(n)                                                                                              \
+  case n:                                                                                                       \
+    return pixel == DDM_PIX_U8                                                                                  \
+               ? step1_go<n, uint8_t>(s, frames, N, precondition, bufs, kxw, ntiles, pack, kxnyq, qt, sm, lo,  \
+                                      hi, out, twW, twH, ctl, maxslots, nwg)                                    \
+               : step1_go<n, uint16_t>(s, frames, N, precondition, bufs, kxw, ntiles, pack, kxnyq, qt, sm, lo, \
+                                       hi, out, twW, twH, ctl, maxslots, nwg);
+  switch (W) {
+    S1_CASE(64) S1_CASE(128) S1_CASE(256) S1_CASE(512)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef S1_CASE
 }
 
 hipError_t launch_qexp(hipStream_t s, const float2* pilot, int np, int64_t nq, int32_t* qexp) {

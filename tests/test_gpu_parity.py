@@ -6,6 +6,7 @@ bit-exact.
 """
 
 import ctypes
+import os
 import sys
 
 import numpy as np
@@ -184,6 +185,24 @@ def test_radial_wide_bins_and_threshold_reuse(gpu):
             first = Dbar.clone()
         if i == 1:
             assert torch.equal(Dbar, first)
+
+
+@pytest.mark.parametrize("W,N,pixel,kw", [(64, 200, "u8", {}), (256, 96, "u16", {}), (512, 40, "u16", {}),
+                                          (128, 64, "u16", {"k2_max": 900}),
+                                          (256, 48, "u16", {"spectrum": "f16"})])
+def test_fused_step_one_matches_split(gpu, W, N, pixel, kw):
+    """Step one in one launch (square frames up to 512) gives the same bits as
+    the separate row and column kernels."""
+    say("case: fused vs split step one", W, N, pixel, kw)
+    frames = synth.brownian_stack(W, W, N, max(4, W * W // 80), 1.5, 40.0, 300.0, 0.3, seed=21, pixel=pixel).cuda()
+    a = gpu.Plan(W, W, N, pixel=pixel, **kw).structure_function(frames)
+    os.environ["DDM_STEP1"] = "split"
+    try:
+        b = gpu.Plan(W, W, N, pixel=pixel, **kw).structure_function(frames)
+    finally:
+        del os.environ["DDM_STEP1"]
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
 
 
 def test_error_paths_leave_outputs_untouched(gpu):
