@@ -520,7 +520,8 @@ static ddm_status run_step_one(ddm_plan_s* p, const void* frames, float2* inter,
     {
       ProfScope ps(p, DDM_KERNEL_STEP1);
       e = launch_step1(p->stream, p->d.pixel, frames, p->W, p->N, p->d.precondition, inter, p->kxw, p->ncol_tiles,
-                       p->kxnyq, qt, sm, s_lo, s_hi, out, p->twW, p->twH, ctl, p->s1_maxslots, p->s1_nwg);
+                       p->kxnyq, qt, sm, s_lo, s_hi, out, p->twW, p->twH, ctl, p->s1_maxslots, p->s1_nwg,
+                       step1_bufs());
     }
     if (e != hipSuccess) return hip_fail(e, "step one launch");
     // the wait-ran-out flag comes back with the next call (not from inside a graph capture)

@@ -98,7 +98,8 @@ hipError_t launch_col(hipStream_t s, const float2* inter, int H, int kxw, int nt
                       int qb, int kxnyq, SpecOut out, const float2* tw, int tws);
 
 // Fused step one (one persistent launch; row intermediates kept per XCD in
-// step1_bufs() frame buffers of each of 8 XCDs at bufs).  Applies to square
+// nbufs >= 2 frame buffers of each of 8 XCDs at bufs; step1_bufs() is the
+// default, DDM_STEP1_BUFS overrides).  Applies to square
 // frames W = H in {64, 128, 256, 512} with full column tiles.  ctl:
 // step1_ctl_words(maxslots) ints of device memory (initialised by the launch);
 // maxslots >= N + nwg / (items per frame) + 4; the last word is an error flag
@@ -110,7 +111,7 @@ __host__ __device__ size_t step1_ctl_words(int maxslots);
 hipError_t launch_step1(hipStream_t s, int pixel, const void* frames, int W, int N, int precondition,
                         float2* bufs, int kxw, int ntiles, int kxnyq, QTable qt, SlotMap sm, int64_t s_lo,
                         int64_t s_hi, SpecOut out, const float2* twW, const float2* twH, int* ctl, int maxslots,
-                        int nwg);
+                        int nwg, int nbufs);
 
 hipError_t launch_qexp(hipStream_t s, const float2* pilot, int np, int64_t nq, int32_t* qexp);
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);

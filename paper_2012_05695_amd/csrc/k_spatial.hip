@@ -20,6 +20,7 @@
 #include <hip/hip_fp16.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "fft.hpp"
 #include "internal.hpp"
@@ -61,7 +62,7 @@ __device__ __forceinline__ uint2 nt_load(const uint2* p) {
   return make_uint2(x[0], x[1]);
 }
 
-template <int W, int E, typename PIX, bool DEV = false, bool NT = false>
+template <int W, int E, typename PIX, bool NT = false>
 __device__ __forceinline__ void row_item(const PIX* __restrict__ frames, int H, int t, int ybase, int nt,
                                          int precondition, float2* __restrict__ out, int kxw, int pack,
                                          const float2* __restrict__ tw, int tws, float2* lds_row, int tx) {
@@ -116,16 +117,7 @@ __device__ __forceinline__ void row_item(const PIX* __restrict__ frames, int H, 
   group_sync<WAVE>();
   float2* o0 = out + (size_t)(2 * p) * kxw;
   float2* o1 = o0 + kxw;
-  // DEV: device-scope stores (written through to memory), for rows that other
-  // workgroups of the same launch read back
-  auto put = [&](float2* o, int k, float2 val) {
-    if constexpr (DEV) {
-      const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(o, (short)0, kxw * 8, 0x00020000);
-      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u32, val), r, (uint32_t)k * 8u, 0, 0x10);
-    } else {
-      o[k] = val;
-    }
-  };
+  auto put = [&](float2* o, int k, float2 val) { o[k] = val; };
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int k = tid + e * T;
@@ -302,10 +294,7 @@ __global__ void __launch_bounds__(CW * (H / E)) k_col(const float2* __restrict__
 // host) instead of hanging.  Control words per XCD: ticket, then per slot the
 // claimed frame (kUnset until published), rows done and columns done.
 // ---------------------------------------------------------------------------
-#ifndef S1_DEV_STORES
-#define S1_DEV_STORES false
-#endif
-constexpr int kStep1Bufs = 3;
+constexpr int kStep1Bufs = 3;  // default frame buffers per XCD (at least 2: see below)
 constexpr int kUnset = -2;
 // bound of one wait, in ticks of the 100 MHz constant clock (0.2 s)
 constexpr uint64_t kWaitTicks = 20000000ull;
@@ -361,7 +350,7 @@ __global__ void __launch_bounds__(16 * (W / E)) k_step1(const PIX* __restrict__ 
                                                          const int32_t* __restrict__ qexp, int32_t* sat,
                                                          const float2* __restrict__ twW,
                                                          const float2* __restrict__ twH, int* __restrict__ ctl,
-                                                         int maxslots) {
+                                                         int maxslots, int nbufs) {
   constexpr int H = W;
   constexpr int T = W / E;
   constexpr int CW = 16;
@@ -417,7 +406,7 @@ __global__ void __launch_bounds__(16 * (W / E)) k_step1(const PIX* __restrict__ 
     const int k = is_row ? st : st - 1;  // the slot this item works on
     const int f = is_row ? fs : fp;
     if (f < 0) continue;  // uniform: this item's slot has no frame
-    float2* buf = bufs + (size_t)(xcc * kStep1Bufs + k % kStep1Bufs) * frame_elems;
+    float2* buf = bufs + (size_t)(xcc * nbufs + k % nbufs) * frame_elems;
     // the thread index, made opaque per item so that the per-thread addresses
     // of both item kinds are not hoisted out of the loop (they would all stay
     // live in registers)
@@ -426,12 +415,12 @@ __global__ void __launch_bounds__(16 * (W / E)) k_step1(const PIX* __restrict__ 
     if (is_row) {
       // the buffer is free once the columns of the slot that last used it
       // have read it (that slot has a frame: claims are in slot order)
-      if (threadIdx.x == 0) s_val = (k < kStep1Bufs || spin_ge(&cols[k - kStep1Bufs], NC, err)) ? 1 : 0;
+      if (threadIdx.x == 0) s_val = (k < nbufs || spin_ge(&cols[k - nbufs], NC, err)) ? 1 : 0;
       __syncthreads();
       if (s_val == 0) break;  // uniform: a wait ran out
       const int ybase = r * 2 * NTR;
-      row_item<W, E, PIX, S1_DEV_STORES, true>(frames, H, f, ybase, NTR, precondition, buf + (size_t)ybase * kxw,
-                                               kxw, pack, twW, 1, lds, tx);
+      row_item<W, E, PIX, true>(frames, H, f, ybase, NTR, precondition, buf + (size_t)ybase * kxw, kxw, pack, twW,
+                                1, lds, tx);
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the rows have reached L2
       __syncthreads();
       if (threadIdx.x == 0) atomicAdd(&rows[k], 1);
@@ -441,7 +430,8 @@ __global__ void __launch_bounds__(16 * (W / E)) k_step1(const PIX* __restrict__ 
       __syncthreads();
       if (s_val == 0) break;  // uniform: a wait ran out
       // device-scope loads: this CU's L1 may still hold lines of the buffer
-      // from the slot that used it before
+      // from the slot that used it before (an acquire fence at device scope
+      // instead, with plain loads, measured 50% slower)
       float2 v[E];
       col_load<H, E, CW, true>(v, buf, kxw, tile * CW + tx % CW, tx / CW);
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the tile is in registers
@@ -594,7 +584,13 @@ hipError_t launch_col(hipStream_t s, const float2* inter, int H, int kxw, int nt
 // ---- fused step one ----
 __host__ __device__ size_t step1_ctl_words(int maxslots) { return (size_t)8 * (1 + 3 * (size_t)maxslots) + 2; }
 
-int step1_bufs() { return kStep1Bufs; }
+int step1_bufs() {
+  static const int env = [] {
+    const char* v = std::getenv("DDM_STEP1_BUFS");
+    return v ? std::atoi(v) : 0;
+  }();
+  return (env >= 2 && env <= 4) ? env : kStep1Bufs;
+}
 
 bool step1_fusable(int W, int H, int ncol_tiles, int kxw) {
   if (W != H || kxw != 16 * ncol_tiles) return false;
@@ -615,17 +611,17 @@ __global__ void k_step1_init(int* ctl, int maxslots) {
 template <int W, typename PIX>
 static hipError_t step1_go(hipStream_t s, const void* frames, int N, int pre, float2* bufs, int kxw, int ntiles,
                            int pack, int kxnyq, QTable qt, SlotMap sm, int s_lo, int s_hi, SpecOut out,
-                           const float2* twW, const float2* twH, int* ctl, int maxslots, int nwg) {
+                           const float2* twW, const float2* twH, int* ctl, int maxslots, int nwg, int nbufs) {
   constexpr int E = 16, T = W / E, CW = 16;
   const size_t lds = std::max((size_t)CW * lds_len<true>(W) * sizeof(float2), (size_t)CW * W * sizeof(float2));
   if (out.qexp != nullptr)
     hipLaunchKernelGGL((k_step1<W, E, PIX, true>), dim3(nwg), dim3(CW * T), lds, s, (const PIX*)frames, N, pre,
                        bufs, kxw, ntiles, pack, kxnyq, qt.qoff, qt.kxcnt, sm.sbase, sm.sN, s_lo, s_hi, out.spec,
-                       out.qexp, out.sat, twW, twH, ctl, maxslots);
+                       out.qexp, out.sat, twW, twH, ctl, maxslots, nbufs);
   else
     hipLaunchKernelGGL((k_step1<W, E, PIX, false>), dim3(nwg), dim3(CW * T), lds, s, (const PIX*)frames, N, pre,
                        bufs, kxw, ntiles, pack, kxnyq, qt.qoff, qt.kxcnt, sm.sbase, sm.sN, s_lo, s_hi, out.spec,
-                       nullptr, nullptr, twW, twH, ctl, maxslots);
+                       nullptr, nullptr, twW, twH, ctl, maxslots, nbufs);
   return hipGetLastError();
 }
 
@@ -638,7 +634,8 @@ int step1_workgroups(int W) {
 hipError_t launch_step1(hipStream_t s, int pixel, const void* frames, int W, int N, int precondition,
                         float2* bufs, int kxw, int ntiles, int kxnyq, QTable qt, SlotMap sm, int64_t s_lo,
                         int64_t s_hi, SpecOut out, const float2* twW, const float2* twH, int* ctl, int maxslots,
-                        int nwg) {
+                        int nwg, int nbufs) {
+  if (nbufs < 2) return hipErrorInvalidValue;  // a row item would wait on a later ticket
   hipLaunchKernelGGL(k_step1_init, dim3(64), dim3(256), 0, s, ctl, maxslots);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -647,9 +644,9 @@ hipError_t launch_step1(hipStream_t s, int pixel, const void* frames, int W, int
   case n:                                                                                                       \
     return pixel == DDM_PIX_U8                                                                                  \
                ? step1_go<n, uint8_t>(s, frames, N, precondition, bufs, kxw, ntiles, pack, kxnyq, qt, sm, lo,  \
-                                      hi, out, twW, twH, ctl, maxslots, nwg)                                    \
+                                      hi, out, twW, twH, ctl, maxslots, nwg, nbufs)                             \
                : step1_go<n, uint16_t>(s, frames, N, precondition, bufs, kxw, ntiles, pack, kxnyq, qt, sm, lo, \
-                                       hi, out, twW, twH, ctl, maxslots, nwg);
+                                       hi, out, twW, twH, ctl, maxslots, nwg, nbufs);
   switch (W) {
     S1_CASE(64) S1_CASE(128) S1_CASE(256) S1_CASE(512)
     default:
