@@ -77,13 +77,18 @@ def time_flops(N, M):
     return 15 * L * math.log2(L) + 20 * L + 13 * M
 
 
+# sources each profiled kernel is built from (a summary is valid while they hash the same)
+PROFILED_SOURCES = {"k_time": ("k_time.hip", "fft.hpp", "internal.hpp"),
+                    "k_step1": ("k_spatial.hip", "fft.hpp", "internal.hpp")}
+
+
 def recorded_traffic(kernel, config):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 summary, or
     None when there is none or the kernel sources changed since it was taken."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "%s_%s_f32.md" % (kernel, config))
-    if not os.path.exists(path):
+    if kernel not in PROFILED_SOURCES or not os.path.exists(path):
         return None
     text = open(path).read()
     m_t = re.search(r"^traffic_bytes_per_launch: (\d+)", text, re.M)
@@ -91,7 +96,7 @@ def recorded_traffic(kernel, config):
     if not (m_t and m_h):
         return None
     src = "".join(open(os.path.join(ROOT, "paper_2012_05695_amd", "csrc", f)).read()
-                  for f in ("k_time.hip", "fft.hpp", "internal.hpp"))
+                  for f in PROFILED_SOURCES[kernel])
     if hashlib.sha256(src.encode()).hexdigest() != m_h.group(1):
         return None
     return int(m_t.group(1))
@@ -274,7 +279,7 @@ def main():
         "kernel_ms_per_step": {k: v[0] for k, v in prof.items()},
         "roofline": dict(roof, **{
             "traffic": (recorded_traffic("k_" + dominant, "%dx%dx%d" % (W, H, N))
-                        if dominant == "time" and args.config == "paper" else None),
+                        if args.config == "paper" else None),
             "avg_launch_ms": avg_launch_ms, "launches": k_n,
             "algorithmic_bytes_per_launch": bytes_per_launch}),
     }
