@@ -203,7 +203,8 @@ enum {
   DDM_FIT_MAXITER = 2,    /* iteration limit reached */
   DDM_FIT_NONFINITE = 4,  /* non-finite data or parameters */
   DDM_FIT_STALLED = 8,    /* no decreasing step found, not stationary */
-  DDM_FIT_FALLBACK = 16   /* refitted from the default start after failing from the given one */
+  DDM_FIT_FALLBACK = 16,  /* refitted from the default start after failing from the given one */
+  DDM_FIT_DEFAULT_START = 32 /* fallback 2: the default start had the lower cost and was used */
 };
 
 /* Sample rows of D at K fractional lags: linear interpolation between the two
@@ -219,7 +220,9 @@ typedef struct ddm_fit_desc {
   uint32_t struct_size; /* = sizeof(ddm_fit_desc) */
   int32_t K;            /* samples per curve, 1..64 */
   int32_t max_iter;     /* Jacobian evaluations per curve (default 200) */
-  int32_t fallback;     /* 1: curves not converged from init_dev are refitted from the default start */
+  int32_t fallback;     /* with init_dev: 0 fit from it; 1 curves not converged from it are refitted
+                           from the default start; 2 each curve starts from whichever of init_dev and
+                           the default start has the lower cost (one fit, no refit) */
   double lambda0;       /* initial Marquardt damping (default 1e-3) */
   double ftol;          /* stop when an accepted step lowers the cost by <= ftol * cost (1e-7) */
   double xtol;          /* stop when |step| <= xtol (|p| + xtol), p = (A, B, log tau) (1e-7) */

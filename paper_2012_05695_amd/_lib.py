@@ -83,6 +83,7 @@ DDM_FIT_MAXITER = 2
 DDM_FIT_NONFINITE = 4
 DDM_FIT_STALLED = 8
 DDM_FIT_FALLBACK = 16
+DDM_FIT_DEFAULT_START = 32
 
 # (name, restype, argtypes) for every symbol of include/ddm.h
 SIGNATURES = [

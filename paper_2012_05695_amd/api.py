@@ -267,6 +267,9 @@ def fit(curves, lags, init=None, fallback=True, max_iter=200, ftol=1e-7, xtol=1e
     """LM fit of every row of curves [n, K] -> (params [n, 3] = A, B, tau; iters [n]; flags [n]).
 
     init: optional [n, 3] float32 (A, B, log tau) start; else the default start.
+    fallback (with init): True refits from the default start the curves that do
+    not converge; "best" starts each curve from whichever of init and the default
+    start has the lower cost; False fits from init only.
     """
     lags = np.ascontiguousarray(np.asarray(lags, dtype=np.float32))
     n, K = curves.shape
@@ -275,7 +278,8 @@ def fit(curves, lags, init=None, fallback=True, max_iter=200, ftol=1e-7, xtol=1e
         _require(init, "init", (torch.float32,), (n, 3), None)
     d = L.FitDesc()
     _lib.ddm_fit_desc_init(ctypes.byref(d))
-    d.K, d.max_iter, d.fallback = K, int(max_iter), 1 if fallback else 0
+    d.K, d.max_iter = K, int(max_iter)
+    d.fallback = 2 if fallback == "best" else (1 if fallback else 0)
     d.ftol, d.xtol, d.gtol, d.lambda0 = float(ftol), float(xtol), float(gtol), float(lambda0)
     with torch.cuda.device(curves.device):
         d.stream = _stream_handle(stream).value

@@ -65,7 +65,8 @@ enum : int32_t {
   LM_FLAG_MAXITER = 2,
   LM_FLAG_NONFINITE = 4,
   LM_FLAG_STALLED = 8,
-  LM_FLAG_FALLBACK = 16
+  LM_FLAG_FALLBACK = 16,
+  LM_FLAG_DEFAULT_START = 32
 };
 
 // ---- launchers (each returns hipSuccess or the launch error) ----
@@ -141,6 +142,6 @@ hipError_t launch_sample(hipStream_t s, const float* D, int64_t n, int M, const 
 
 hipError_t launch_lm(hipStream_t s, const float* Y, int64_t n, const LagSet& lags, const float* init,
                      const LmParams& prm, const int32_t* only_if_flag_clear, float* params,
-                     int32_t* iters, int32_t* flags);
+                     int32_t* iters, int32_t* flags, bool best_start = false);
 
 }  // namespace ddm

@@ -59,11 +59,13 @@ __device__ __forceinline__ double lm_cost(const float (&y)[K], const LagSet& lag
   return c;
 }
 
+// best_start: with init given, start from whichever of init and the default
+// start has the lower cost (LM_FLAG_DEFAULT_START when the default wins).
 __global__ void __launch_bounds__(64) k_lm(const float* __restrict__ Y, int64_t n, LagSet lags,
                                            const float* __restrict__ init, LmParams prm,
                                            const int32_t* only_if_flag_clear,  // may alias flags
                                            float* __restrict__ params, int32_t* iters,
-                                           int32_t* flags) {
+                                           int32_t* flags, int best_start) {
   constexpr int K = kMaxK;
   __shared__ float tile[64 * (K + 1)];
   const int64_t c0 = (int64_t)blockIdx.x * 64;
@@ -90,20 +92,26 @@ __global__ void __launch_bounds__(64) k_lm(const float* __restrict__ Y, int64_t 
       ymax = fmax(ymax, (double)y[j]);
       finite = finite && isfinite(y[j]);
     }
-  double A, B, th;
-  if (init != nullptr && only_if_flag_clear == nullptr) {
-    A = init[cid * 3 + 0];
-    B = init[cid * 3 + 1];
-    th = init[cid * 3 + 2];
-  } else {
-    // default initialisation on the curve normalised by its maximum
-    const double c = (isfinite(ymax) && ymax > 0.0) ? ymax : 1.0;
-    const double B0 = (double)y[0] / c;
-    A = (1.0 - B0) * c;
-    B = B0 * c;
-    th = 0.5 * (log((double)lags.m[0]) + log((double)lags.m[k - 1]));
-  }
+  // default initialisation on the curve normalised by its maximum
+  const double c = (isfinite(ymax) && ymax > 0.0) ? ymax : 1.0;
+  const double B0 = (double)y[0] / c;
+  double A = (1.0 - B0) * c, B = B0 * c, th = 0.5 * (log((double)lags.m[0]) + log((double)lags.m[k - 1]));
   int32_t fl = 0, it = 0;
+  if (init != nullptr && only_if_flag_clear == nullptr) {
+    const double Ai = init[cid * 3 + 0], Bi = init[cid * 3 + 1], thi = init[cid * 3 + 2];
+    bool take = true;
+    if (best_start) {
+      const double ci = lm_cost<K>(y, lags, k, Ai, Bi, thi), cd = lm_cost<K>(y, lags, k, A, B, th);
+      take = isfinite(ci) && !(cd < ci);  // ties go to the given start
+    }
+    if (take) {
+      A = Ai;
+      B = Bi;
+      th = thi;
+    } else {
+      fl |= LM_FLAG_DEFAULT_START;
+    }
+  }
   if (!finite || !isfinite(A) || !isfinite(B) || !isfinite(th)) {
     fl = LM_FLAG_NONFINITE;
   } else {
@@ -199,10 +207,10 @@ hipError_t launch_sample(hipStream_t s, const float* D, int64_t n, int M, const 
 
 hipError_t launch_lm(hipStream_t s, const float* Y, int64_t n, const LagSet& lags, const float* init,
                      const LmParams& prm, const int32_t* only_if_flag_clear, float* params,
-                     int32_t* iters, int32_t* flags) {
+                     int32_t* iters, int32_t* flags, bool best_start) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_lm, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, Y, n, lags, init, prm,
-                     only_if_flag_clear, params, iters, flags);
+                     only_if_flag_clear, params, iters, flags, best_start ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -83,3 +83,30 @@ def test_fit_init_and_fallback(gpu):
     fb = fb.cpu().numpy()
     assert np.all(fb[:10] & 16) and np.all(fb[:10] & 1)
     assert not np.any(fb[10:] & 16)
+
+
+def test_fit_best_start(gpu):
+    """fallback="best": each curve starts from the lower-cost of the given and the
+    default start (flag 32 when the default wins), then one fit; results match
+    the FP64 oracle fitted from the same start."""
+    say("case: LM best start")
+    Y, P, m = synth_curves(256, noise=0.01, seed=6)
+    good = np.stack([P[:, 0], P[:, 1], np.log(P[:, 2])], 1).astype(np.float32)
+    start = good.copy()
+    start[::2, 2] += 6.0                                # every other start is far off in tau
+    pb, ib, fb = gpu.fit(torch.from_numpy(Y).cuda(), m, init=torch.from_numpy(start).cuda(), fallback="best")
+    pb, fb = pb.cpu().numpy(), fb.cpu().numpy()
+    mm = m.astype(np.float64)
+    chose_default = (fb & 32) != 0
+    assert not np.any(fb & 16)
+    for i in range(0, 256, 17):
+        # the choice itself: the lower of the two initial costs (FP64 here)
+        d0 = lm.default_init(Y[i].astype(np.float64), mm)
+        ci = np.sum((lm.model(start[i].astype(np.float64), mm) - Y[i]) ** 2)
+        cd = np.sum((lm.model(d0, mm) - Y[i]) ** 2)
+        if abs(ci - cd) > 1e-3 * max(ci, cd):
+            assert chose_default[i] == (cd < ci), i
+        p0 = d0 if chose_default[i] else start[i].astype(np.float64)
+        po, co, io, fo = lm.lm_fit(Y[i].astype(np.float64), mm, p0)
+        cg = np.sum((lm.model((pb[i, 0], pb[i, 1], np.log(pb[i, 2])), mm) - Y[i]) ** 2)
+        assert cg <= co * (1 + 1e-4) + 1e-10, (i, cg, co)

@@ -23,8 +23,12 @@ def test_learned_start_beats_default(gpu):
     curves, scale, (A, B, tau) = learn.stack_curves(128, 128, 512, D0, n_spots, a, 7, lags)
     res = learn.compare(curves, lags, init, truth_tau=tau, tau_window=(2.0, 128.0))
     print(res, flush=True)
-    m = res["measurable"]
-    assert m["learned"]["mean_iters"] < 0.9 * m["default"]["mean_iters"]
-    assert m["learned"]["converged"] >= m["default"]["converged"] - 0.005
-    assert m["learned_cost_not_worse"] >= 0.97
-    assert res["all"]["learned"]["converged"] >= res["all"]["default"]["converged"] - 0.005
+    m, a = res["measurable"], res["all"]
+    for key in ("learned", "learned_refit"):
+        assert m[key]["mean_iters"] < 0.9 * m["default"]["mean_iters"]
+        assert m[key]["converged"] >= m["default"]["converged"] - 0.005
+        assert m[key]["cost_not_worse"] >= 0.97
+    # refitting the failures keeps every curve the default start converges
+    assert a["learned_refit"]["converged"] >= a["default"]["converged"] - 0.005
+    # the lower-cost start with one fit costs about one fit more than the network
+    assert res["learned_ms"] < res["learned_refit_ms"]
