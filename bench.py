@@ -38,6 +38,9 @@ def parse():
                     help="kx columns of the oracle sample (0: all, i.e. the whole workload)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the tau-fit leg (network training + LM vs MLP+LM on 1024x1024x2048)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-stacks leg (graph launch vs a loop of single plans)")
+    ap.add_argument("--batched-stacks", type=int, default=16)
     ap.add_argument("--learned-curves", type=int, default=1_000_000)
     ap.add_argument("--learned-epochs", type=int, default=30)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -124,7 +127,16 @@ def cpu_baseline(frames_cpu, ncols, nq_total):
         sample = ("kx columns 0..%d x all %d ky (%d of %d q), all %d frames and lags; "
                   "%.2f s measured, extrapolated linearly in q to %.0f s" %
                   (ncols - 1, H, nq_s, nq_total, N, dt, full_s))
-    return {"value": N / full_s, "unit": "frames/s", "cores": threads, "kind": "oracle", "sample": sample}
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": N / full_s, "unit": "frames/s", "cores": threads, "kind": "oracle", "sample": sample,
+            "cpu": cpu, "host_cpus": os.cpu_count()}
 
 
 def learned_leg(log):
@@ -159,6 +171,106 @@ def learned_leg(log):
             "all": res["all"], "measurable_tau_2_to_512": res.get("measurable"),
             "training": {"curves": args.learned_curves, "epochs": args.learned_epochs,
                          "final_loss": losses[-1], "data_s": t1 - t0, "train_s": t2 - t1}}
+
+
+def kernel_roof(kind, ms_per_launch, launches_per_step, W, H, N, M, nq, pix_bytes):
+    """Roofline entry of one kernel from its average launch time: achieved HBM
+    rate on its algorithmic bytes, and for the time kernel also its FP32 rate;
+    "bound" is the roof that needs the longer time at peak."""
+    per, _ = algorithmic_bytes(W, H, N, M, nq, pix_bytes)
+    if kind in ("row", "col", "step1"):
+        nbytes = per[kind] * N / launches_per_step
+    elif kind == "time":
+        nbytes = per["time"] * nq / launches_per_step
+    else:
+        nbytes = nq * M * 4 / launches_per_step
+    gbs = nbytes / (ms_per_launch * 1e-3) / 1e9
+    roof = {"kernel": kind, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": nbytes,
+            "avg_launch_ms": ms_per_launch}
+    if kind == "time":
+        flops = time_flops(N, M) * nq / launches_per_step
+        if flops / (ALU_PEAK_TFLOPS * 1e12) > nbytes / (HBM_PEAK_GBS * 1e9):
+            tf = flops / (ms_per_launch * 1e-3) / 1e12
+            roof.update({"bound": "alu", "achieved": tf, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tf / ALU_PEAK_TFLOPS, "algorithmic_flops_per_launch": flops,
+                         "hbm_achieved_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS})
+    return roof
+
+
+def copy_bandwidth():
+    """GB/s (bytes read + written) of a 1 GiB device-to-device torch copy: what
+    a plain streaming kernel reaches on this machine."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(5):
+        dst.copy_(src)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / 5
+    del src, dst
+    return 2 * (1 << 30) / (ms * 1e-3) / 1e9
+
+
+def batched_leg(n_stacks, log):
+    """a7: stacks of mixed shapes (W = H in {128, 256, 384, 512, 1024}, N log-uniform in
+    [256, 4096], D0 log-uniform in [0.01, 10], 2000 spots per 512x512, uint16) in one graph
+    launch, against the same stacks as a loop of single-plan calls on one stream."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2012_05695_amd import api, synth
+    rng = np.random.default_rng(64)
+    shapes, frames = [], []
+    for i in range(n_stacks):
+        w = int(rng.choice([128, 256, 384, 512, 1024]))
+        n = int(round(math.exp(rng.uniform(math.log(256), math.log(4096)))))
+        d0 = math.exp(rng.uniform(math.log(0.01), math.log(10.0)))
+        nsp = max(1, int(round(2000 * w * w / (512 * 512))))
+        frames.append(synth.brownian_stack(w, w, n, nsp, 1.5, 40.0, 800.0, d0, seed=5000 + i, pixel="u16",
+                                           device="cuda"))
+        shapes.append((w, w, n))
+    torch.cuda.synchronize()
+    total = sum(n for _, _, n in shapes)
+    log("batched leg: %d stacks, %d frames, %.1f GB of frames" %
+        (n_stacks, total, sum(f.numel() * 2 for f in frames) / 1e9))
+    batch = api.Batch(shapes, lanes=4)
+    batch.allocate_workspace()
+    outs = batch.structure_function(frames)
+    # the loop's plans run one after another on one stream: one shared workspace
+    plans = [api.Plan(w, h, n) for (w, h, n) in shapes]
+    shared = torch.empty(max(p.workspace_size()[1] for p in plans), dtype=torch.uint8, device="cuda")
+    for p in plans:
+        p.set_workspace(shared)
+    for p, f, o in zip(plans, frames, outs):
+        p.structure_function(f, out=o)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    reps = 3
+    ev[0].record()
+    for _ in range(reps):
+        batch.structure_function(frames, outs)
+    ev[1].record()
+    for _ in range(reps):
+        for p, f, o in zip(plans, frames, outs):
+            p.structure_function(f, out=o)
+    ev[2].record()
+    torch.cuda.synchronize()
+    t_b = ev[0].elapsed_time(ev[1]) / reps
+    t_l = ev[1].elapsed_time(ev[2]) / reps
+    for p in plans:
+        p.close()
+    batch.close()
+    del frames, outs, shared
+    torch.cuda.empty_cache()
+    return {"stacks": n_stacks, "shapes": ["%dx%dx%d" % s for s in shapes], "frames": total,
+            "batched_ms": t_b, "loop_ms": t_l, "batched_frames_per_s": total / (t_b * 1e-3),
+            "loop_frames_per_s": total / (t_l * 1e-3),
+            "recipe": "%d stacks (of the 64 in the batched workload's recipe), seeds 5000+i" % n_stacks}
 
 
 def main():
@@ -286,10 +398,34 @@ def main():
             "avg_launch_ms": avg_launch_ms, "launches": k_n,
             "algorithmic_bytes_per_launch": bytes_per_launch}),
     }
+    # every kernel of the step against its roof (from the profiling pass)
+    out["kernel_rooflines"] = {k: kernel_roof(k, v[0] / v[1], v[1], W, H, N, M, nq, pix_bytes)
+                               for k, v in prof.items()}
+    out["copy_GBs"] = copy_bandwidth()
+    # the same workload with the FP16 per-q-scaled spectra store
+    plan16 = api.Plan(W, H, N, pixel=recipe["pixel"], spectrum="f16")
+    plan16.allocate_workspace()
+    for _ in range(2):
+        plan16.structure_function(frames, out=D)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        plan16.structure_function(frames, out=D)
+        plan16.radial_average(D, thr, bin_of_q=False)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms16 = ev0.elapsed_time(ev1) / args.steps
+    out["f16_store"] = {"ms_per_step": ms16, "frames_per_s": N / (ms16 * 1e-3),
+                        "saturated_values": int(plan16.fp16_saturations())}
+    plan16.close()
     frames_cpu = frames.cpu() if not args.no_cpu_baseline else None
     del frames, D
     plan.close()
     torch.cuda.empty_cache()
+    if not args.no_batched:
+        print("bench: batched leg (graph launch vs loop)", file=sys.stderr, flush=True)
+        out["batched"] = batched_leg(args.batched_stacks,
+                                     lambda m: print("bench: " + m, file=sys.stderr, flush=True))
     if not args.no_learned:
         print("bench: tau-fit leg (training the start network, then LM vs MLP+LM)", file=sys.stderr,
               flush=True)
