@@ -120,12 +120,19 @@ ddm_status ddm_plan_set_workspace(ddm_plan_t plan, void* workspace_dev, size_t b
 
 /* The full path: frames_dev [N][H][W] (uint8 or uint16 per the plan, row-major,
  * device, 16-byte aligned) -> D_dev [n_q][M] float32 (device), D(q, m) of Eq. (1).
- * Requires a workspace.  Returns DDM_WARN_FP16_SATURATED (result written) if
- * the FP16 spectrum store clipped values. */
+ * Requires a workspace.
+ * Device-side outcomes come back without stalling the host: each call enqueues
+ * a copy of them, and each later call takes in those that have completed,
+ * checked without waiting (the host waits only when it is 4 calls ahead of the
+ * device).  From then on, the call returns DDM_WARN_FP16_SATURATED (result
+ * written) once any FP16 spectrum value has been clipped since the plan was
+ * created, and returns DDM_ERR_HIP (enqueuing nothing) once for an earlier
+ * call whose single-launch step one ran out of time in a wait (that call's D
+ * is not valid).  Calls made inside a HIP graph capture hand nothing back. */
 ddm_status ddm_structure_function(ddm_plan_t plan, const void* frames_dev, float* D_dev);
 
 /* FP16 spectrum store: total number of spectrum components clipped to
- * +-65504 since the plan was created (waits for the last call's count). */
+ * +-65504 since the plan was created (waits for every call enqueued so far). */
 ddm_status ddm_plan_fp16_saturations(ddm_plan_t plan, int64_t* count);
 
 /* Step one only: frames_dev [N][H][W] -> spectra_dev [n_q][N] complex float32

@@ -58,6 +58,7 @@ ddm_status api_fail(ddm_status st, const char* fmt, ...) {
 namespace {
 
 constexpr size_t kInterTargetBytes = 64u << 20;  // row-transform intermediate per batch
+constexpr int kReadback = 4;                      // calls in flight before the host waits
 
 }  // namespace
 
@@ -73,12 +74,9 @@ struct ddm_plan_s {
   int kx_needed, cw, kxw, ncol_tiles;
   int kxnyq;  // W/2 when the Nyquist column is kept (packed with kx = 0), else -1
   // step one in one launch (square frames up to 512): workgroups, control
-  // slots, workspace frames it needs, and the error flag of the last launch
+  // slots, workspace frames it needs
   bool fused;
   int s1_nwg, s1_maxslots, s1_frames;
-  int32_t* s1_err_host;  // pinned
-  hipEvent_t s1_ev;
-  bool s1_pending;
   size_t frame_inter_bytes;
   int fb_target;
   hipStream_t stream;
@@ -87,6 +85,7 @@ struct ddm_plan_s {
   float2 *twW, *twH, *twT;
   double* ramp;  // 1/(N-m), m < N, FP64 (the ramp vector of Appendix B)
   int32_t *qoff_d, *kxcnt_d;
+  int32_t* pilot_d;  // FP16 store: the pilot frame numbers
   // blocked spectra store: slot tables (every row starts a new block of 16,
   // the Nyquist column has its own rows of blocks), slot -> wave vector
   int64_t nslots;
@@ -107,10 +106,17 @@ struct ddm_plan_s {
   // FP16 spectrum store
   bool f16;
   std::vector<int> pilot;  // pilot frames that fix the per-q scale
-  int32_t* sat_host;       // pinned: saturation count of the last call
-  hipEvent_t sat_ev;
-  bool sat_pending;
-  int64_t sat_total;
+  int64_t sat_total;       // saturation counts folded in so far
+  // what a call hands back to the host (step-one error flag, FP16 saturation
+  // count): a ring of pinned slots, each with the event after its copies.  A
+  // slot is folded in once its event has completed, checked without waiting at
+  // the start of each call; the host waits only to reuse a slot, i.e. when it
+  // runs kReadback calls ahead of the device.
+  int32_t* rb_host;  // pinned [kReadback][2]: error flag, saturation count
+  hipEvent_t rb_ev[kReadback];
+  bool rb_pending[kReadback];
+  int rb_next;
+  bool s1_failed;  // a folded slot carried a step-one error not yet reported
   // profiling: event pairs around launches of the kinds in prof_mask
   uint32_t prof_mask;
   struct Rec { uint32_t kind; hipEvent_t a, b; };
@@ -319,8 +325,14 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
     if (p->kxnyq > 0 && p->kxcnt[ky] == W / 2 + 1) qmap[(size_t)p->sN + ky] = p->qoff[ky] + W / 2;
   }
   p->stream = (hipStream_t)desc->stream;
+  p->f16 = desc->spectrum == DDM_SPEC_F16_QSCALED;
+  for (int j = 1; j <= 7; ++j) p->pilot.push_back((int)((int64_t)j * N / 8));
+  p->pilot.push_back(N - 1);
+  std::sort(p->pilot.begin(), p->pilot.end());
+  p->pilot.erase(std::unique(p->pilot.begin(), p->pilot.end()), p->pilot.end());
 
-  // device tables: twiddles for W, H, 2L; q offsets and counts per ky row
+  // device tables: twiddles for W, H, 2L; q offsets and counts per ky row;
+  // slot map; pilot frames
   const size_t ntw = (size_t)W + H + 2 * (size_t)p->L;
   std::vector<float2> tw(ntw);
   fill_twiddles(tw, 0, W);
@@ -331,7 +343,8 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
   std::vector<double> ramp(N);
   for (int m = 0; m < N; ++m) ramp[m] = 1.0 / (double)(N - m);
   const size_t qmap_bytes = align256((size_t)p->nslots * sizeof(int32_t));
-  const size_t tab_bytes = tw_bytes + ramp_bytes + 3 * align256(H * sizeof(int32_t)) + qmap_bytes;
+  const size_t pilot_bytes = align256(p->pilot.size() * sizeof(int32_t));
+  const size_t tab_bytes = tw_bytes + ramp_bytes + 3 * align256(H * sizeof(int32_t)) + qmap_bytes + pilot_bytes;
   hipError_t e = hipMalloc(&p->dev_tables, tab_bytes);
   if (e != hipSuccess) {
     delete p;
@@ -346,12 +359,15 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
   p->kxcnt_d = (int32_t*)(base + tw_bytes + ramp_bytes + align256(H * sizeof(int32_t)));
   p->sbase_d = (int32_t*)(base + tw_bytes + ramp_bytes + 2 * align256(H * sizeof(int32_t)));
   p->qmap_d = (int32_t*)(base + tw_bytes + ramp_bytes + 3 * align256(H * sizeof(int32_t)));
+  p->pilot_d = (int32_t*)((char*)p->qmap_d + qmap_bytes);
   if ((e = hipMemcpy(p->twW, tw.data(), ntw * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(p->ramp, ramp.data(), N * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(p->qoff_d, p->qoff.data(), H * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(p->kxcnt_d, p->kxcnt.data(), H * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(p->sbase_d, p->sbase.data(), H * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(p->qmap_d, qmap.data(), (size_t)p->nslots * sizeof(int32_t), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(p->pilot_d, p->pilot.data(), p->pilot.size() * sizeof(int32_t), hipMemcpyHostToDevice)) !=
           hipSuccess) {
     hipFree(p->dev_tables);
     delete p;
@@ -368,39 +384,27 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
     p->prof_ms[i] = 0.0;
     p->prof_n[i] = 0;
   }
-  p->f16 = desc->spectrum == DDM_SPEC_F16_QSCALED;
-  for (int j = 1; j <= 7; ++j) p->pilot.push_back((int)((int64_t)j * N / 8));
-  p->pilot.push_back(N - 1);
-  std::sort(p->pilot.begin(), p->pilot.end());
-  p->pilot.erase(std::unique(p->pilot.begin(), p->pilot.end()), p->pilot.end());
-  p->sat_host = nullptr;
-  p->sat_ev = nullptr;
-  p->sat_pending = false;
   p->sat_total = 0;
-  if (p->f16) {
-    if ((e = hipHostMalloc((void**)&p->sat_host, sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&p->sat_ev, hipEventDisableTiming)) != hipSuccess) {
-      if (p->sat_host) hipHostFree(p->sat_host);
-      hipFree(p->dev_tables);
-      delete p;
-      return hip_fail(e, "FP16 counter setup");
-    }
-    *p->sat_host = 0;
+  p->rb_host = nullptr;
+  p->rb_next = 0;
+  p->s1_failed = false;
+  for (int i = 0; i < kReadback; ++i) {
+    p->rb_ev[i] = nullptr;
+    p->rb_pending[i] = false;
   }
-  p->s1_err_host = nullptr;
-  p->s1_ev = nullptr;
-  p->s1_pending = false;
-  if (p->fused) {
-    if ((e = hipHostMalloc((void**)&p->s1_err_host, sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&p->s1_ev, hipEventDisableTiming)) != hipSuccess) {
-      if (p->s1_err_host) hipHostFree(p->s1_err_host);
-      if (p->sat_ev) hipEventDestroy(p->sat_ev);
-      if (p->sat_host) hipHostFree(p->sat_host);
+  if (p->f16 || p->fused) {
+    e = hipHostMalloc((void**)&p->rb_host, 2 * kReadback * sizeof(int32_t), hipHostMallocDefault);
+    for (int i = 0; i < kReadback && e == hipSuccess; ++i)
+      e = hipEventCreateWithFlags(&p->rb_ev[i], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      for (int i = 0; i < kReadback; ++i)
+        if (p->rb_ev[i]) hipEventDestroy(p->rb_ev[i]);
+      if (p->rb_host) hipHostFree(p->rb_host);
       hipFree(p->dev_tables);
       delete p;
-      return hip_fail(e, "step one flag setup");
+      return hip_fail(e, "readback setup");
     }
-    *p->s1_err_host = 0;
+    std::memset(p->rb_host, 0, 2 * kReadback * sizeof(int32_t));
   }
   *out = p;
   g_err.clear();
@@ -412,10 +416,9 @@ ddm_status ddm_plan_destroy(ddm_plan_t p) {
   if (p->magic != kPlanMagic) return fail(DDM_ERR_STATE, "plan handle is not a live plan");
   hipStreamSynchronize(p->stream);
   prof_drain(p);
-  if (p->sat_ev) hipEventDestroy(p->sat_ev);
-  if (p->sat_host) hipHostFree(p->sat_host);
-  if (p->s1_ev) hipEventDestroy(p->s1_ev);
-  if (p->s1_err_host) hipHostFree(p->s1_err_host);
+  for (int i = 0; i < kReadback; ++i)
+    if (p->rb_ev[i]) hipEventDestroy(p->rb_ev[i]);
+  if (p->rb_host) hipHostFree(p->rb_host);
   p->magic = 0;
   if (p->dev_tables) hipFree(p->dev_tables);
   if (p->thr_d) hipFree(p->thr_d);
@@ -508,32 +511,35 @@ static void partition(const ddm_plan_s* p, int* fb, int64_t* gblocks) {
   *gblocks = g;
 }
 
+// Step one in one launch: the plan is fused and the workspace holds its frame
+// buffers and control words (blocked store only).
+static bool step_one_fused(const ddm_plan_s* p, int fb, int qb) {
+  return p->fused && qb == kSpecQB && fb >= p->s1_frames;
+}
+
+// Control words of the fused step one, after its frame buffers; the last word
+// is its error flag.
+static int* step_one_ctl(const ddm_plan_s* p, float2* inter) {
+  return (int*)(inter + (size_t)8 * step1_bufs() * ((size_t)p->H * p->kxw));
+}
+
 // Step one for frames 0..N-1 into slots [s_lo, s_hi): the blocked store
 // (qb = 16, the plan's slot tables) or the plain [q][N] layout (qb = 1, slot = q).
+// first: the first group of a call (the fused form clears its error flag;
+// later groups keep it, so the flag covers the whole call).
 static ddm_status run_step_one(ddm_plan_s* p, const void* frames, float2* inter, int fb, int64_t s_lo,
-                               int64_t s_hi, int qb, SpecOut out) {
+                               int64_t s_hi, int qb, SpecOut out, bool first) {
   QTable qt{p->qoff_d, p->kxcnt_d};
   const SlotMap sm = (qb == 1) ? SlotMap{p->qoff_d, -1} : SlotMap{p->sbase_d, p->sN};
-  if (p->fused && qb == kSpecQB && fb >= p->s1_frames) {
-    int* ctl = (int*)(inter + (size_t)8 * step1_bufs() * ((size_t)p->H * p->kxw));
+  if (step_one_fused(p, fb, qb)) {
     hipError_t e;
     {
       ProfScope ps(p, DDM_KERNEL_STEP1);
       e = launch_step1(p->stream, p->d.pixel, frames, p->W, p->N, p->d.precondition, inter, p->kxw, p->ncol_tiles,
-                       p->kxnyq, qt, sm, s_lo, s_hi, out, p->twW, p->twH, ctl, p->s1_maxslots, p->s1_nwg,
-                       step1_bufs());
+                       p->kxnyq, qt, sm, s_lo, s_hi, out, p->twW, p->twH, step_one_ctl(p, inter),
+                       p->s1_maxslots, p->s1_nwg, step1_bufs(), first);
     }
     if (e != hipSuccess) return hip_fail(e, "step one launch");
-    // the wait-ran-out flag comes back with the next call (not from inside a graph capture)
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    e = hipStreamIsCapturing(p->stream, &cs);
-    if (e == hipSuccess && cs == hipStreamCaptureStatusNone) {
-      e = hipMemcpyAsync(p->s1_err_host, ctl + step1_ctl_words(p->s1_maxslots) - 1, sizeof(int32_t),
-                         hipMemcpyDeviceToHost, p->stream);
-      if (e == hipSuccess) e = hipEventRecord(p->s1_ev, p->stream);
-      if (e == hipSuccess) p->s1_pending = true;
-    }
-    if (e != hipSuccess) return hip_fail(e, "step one flag copy");
     return DDM_OK;
   }
   for (int t0 = 0; t0 < p->N; t0 += fb) {
@@ -541,7 +547,7 @@ static ddm_status run_step_one(ddm_plan_s* p, const void* frames, float2* inter,
     hipError_t e;
     {
       ProfScope ps(p, DDM_KERNEL_ROW);
-      e = launch_row(p->stream, p->d.pixel, frames, p->W, p->H, t0, nf, p->d.precondition,
+      e = launch_row(p->stream, p->d.pixel, frames, p->W, p->H, t0, nullptr, nf, p->d.precondition,
                      inter, p->kxw, p->kxnyq > 0, p->twW, 1);
     }
     if (e != hipSuccess) return hip_fail(e, "row transform launch");
@@ -555,17 +561,19 @@ static ddm_status run_step_one(ddm_plan_s* p, const void* frames, float2* inter,
   return DDM_OK;
 }
 
-// FP16 store: transform the pilot frames (FP32, [nq][np]) and derive the per-q
-// exponents; clear the saturation counter.
-static ddm_status run_pilot(ddm_plan_s* p, const void* frames, float2* inter, float2* pilot, int32_t* qexp,
-                            int32_t* sat) {
+// FP16 store: transform the pilot frames (FP32, [nq][np]) as many at a time as
+// the intermediate holds, derive the per-q exponents, clear the saturation
+// counter.
+static ddm_status run_pilot(ddm_plan_s* p, const void* frames, float2* inter, int fb, float2* pilot,
+                            int32_t* qexp, int32_t* sat) {
   QTable qt{p->qoff_d, p->kxcnt_d};
   const int np = (int)p->pilot.size();
-  for (int i = 0; i < np; ++i) {
-    hipError_t e = launch_row(p->stream, p->d.pixel, frames, p->W, p->H, p->pilot[i], 1, p->d.precondition,
-                              inter, p->kxw, p->kxnyq > 0, p->twW, 1);
+  for (int i0 = 0; i0 < np; i0 += fb) {
+    const int nf = std::min(fb, np - i0);
+    hipError_t e = launch_row(p->stream, p->d.pixel, frames, p->W, p->H, 0, p->pilot_d + i0, nf,
+                              p->d.precondition, inter, p->kxw, p->kxnyq > 0, p->twW, 1);
     if (e == hipSuccess)
-      e = launch_col(p->stream, inter, p->H, p->kxw, p->ncol_tiles, i, 1, np, qt, SlotMap{p->qoff_d, -1}, 0,
+      e = launch_col(p->stream, inter, p->H, p->kxw, p->ncol_tiles, i0, nf, np, qt, SlotMap{p->qoff_d, -1}, 0,
                      p->nq, 1, p->kxnyq, SpecOut{pilot, nullptr, nullptr}, p->twH, 1);
     if (e != hipSuccess) return hip_fail(e, "pilot transform launch");
   }
@@ -575,27 +583,52 @@ static ddm_status run_pilot(ddm_plan_s* p, const void* frames, float2* inter, fl
   return DDM_OK;
 }
 
-// Fold a finished saturation count into the plan's sticky total.
-// Result of the last fused step one: DDM_ERR_HIP if one of its waits ran out.
-static ddm_status s1_collect(ddm_plan_s* p) {
-  if (!p->s1_pending) return DDM_OK;
-  hipError_t e = hipEventSynchronize(p->s1_ev);
-  if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-  p->s1_pending = false;
-  if (*p->s1_err_host != 0) {
-    *p->s1_err_host = 0;
-    return fail(DDM_ERR_HIP, "step one: a wait between its row and column work ran out; the result of the previous call is not valid");
-  }
-  return DDM_OK;
+// Fold readback slot i (its copies have completed).
+static void rb_fold(ddm_plan_s* p, int i) {
+  const int32_t* v = p->rb_host + 2 * i;
+  if (v[0] != 0) p->s1_failed = true;
+  p->sat_total += v[1];
+  p->rb_pending[i] = false;
 }
 
-static hipError_t sat_collect(ddm_plan_s* p) {
-  if (!p->sat_pending) return hipSuccess;
-  hipError_t e = hipEventSynchronize(p->sat_ev);
-  if (e != hipSuccess) return e;
-  p->sat_total += *p->sat_host;
-  p->sat_pending = false;
+// Fold every slot whose copies have completed; wait for them all when `wait`.
+static hipError_t rb_collect(ddm_plan_s* p, bool wait) {
+  for (int k = 0; k < kReadback; ++k) {
+    const int i = (p->rb_next + k) % kReadback;  // oldest first
+    if (!p->rb_pending[i]) continue;
+    hipError_t e = wait ? hipEventSynchronize(p->rb_ev[i]) : hipEventQuery(p->rb_ev[i]);
+    if (e == hipErrorNotReady) return hipSuccess;  // later slots are later still
+    if (e != hipSuccess) return e;
+    rb_fold(p, i);
+  }
   return hipSuccess;
+}
+
+// Enqueue the copies of this call's error flag (err_dev, or 0 if NULL) and
+// saturation count (sat_dev, or 0) into the next slot.
+static hipError_t rb_push(ddm_plan_s* p, const int32_t* err_dev, const int32_t* sat_dev) {
+  const int i = p->rb_next;
+  if (p->rb_pending[i]) {
+    hipError_t e = hipEventSynchronize(p->rb_ev[i]);
+    if (e != hipSuccess) return e;
+    rb_fold(p, i);
+  }
+  int32_t* v = p->rb_host + 2 * i;
+  v[0] = v[1] = 0;
+  hipError_t e = hipSuccess;
+  if (err_dev != nullptr) e = hipMemcpyAsync(v, err_dev, sizeof(int32_t), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess && sat_dev != nullptr)
+    e = hipMemcpyAsync(v + 1, sat_dev, sizeof(int32_t), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipEventRecord(p->rb_ev[i], p->stream);
+  if (e != hipSuccess) return e;
+  p->rb_pending[i] = true;
+  p->rb_next = (i + 1) % kReadback;
+  return hipSuccess;
+}
+
+static bool capturing(const ddm_plan_s* p) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(p->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
 }
 
 ddm_status ddm_structure_function(ddm_plan_t p, const void* frames, float* D) {
@@ -604,10 +637,15 @@ ddm_status ddm_structure_function(ddm_plan_t p, const void* frames, float* D) {
   if (frames == nullptr || D == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "frames/D is NULL");
   if (((uintptr_t)frames & 15) != 0) return fail(DDM_ERR_INVALID_ARGUMENT, "frames must be 16-byte aligned");
   if (p->ws == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "no workspace attached (ddm_plan_set_workspace)");
-  st = s1_collect(p);
-  if (st != DDM_OK) return st;
-  hipError_t e = sat_collect(p);
-  if (e != hipSuccess) return hip_fail(e, "saturation count");
+  // nothing comes back from a call made inside a graph capture
+  const bool readback = p->rb_host != nullptr && !capturing(p);
+  hipError_t e;
+  if (readback && (e = rb_collect(p, false)) != hipSuccess) return hip_fail(e, "readback");
+  if (p->s1_failed) {
+    p->s1_failed = false;
+    return fail(DDM_ERR_HIP, "step one: a wait between its row and column work ran out in an earlier call; "
+                             "that call's result is not valid");
+  }
   int fb;
   int64_t gblocks;
   partition(p, &fb, &gblocks);
@@ -623,13 +661,13 @@ ddm_status ddm_structure_function(ddm_plan_t p, const void* frames, float* D) {
   float2* inter = (float2*)base;
   void* spec = base + align256((size_t)fb * p->frame_inter_bytes);
   if (p->f16) {
-    st = run_pilot(p, frames, inter, pilot, qexp, sat);
+    st = run_pilot(p, frames, inter, fb, pilot, qexp, sat);
     if (st != DDM_OK) return st;
   }
   const int64_t gs = gblocks * kSpecQB;
   for (int64_t s_lo = 0; s_lo < p->nslots; s_lo += gs) {
     const int64_t s_hi = std::min(p->nslots, s_lo + gs);
-    st = run_step_one(p, frames, inter, fb, s_lo, s_hi, kSpecQB, SpecOut{spec, qexp, sat});
+    st = run_step_one(p, frames, inter, fb, s_lo, s_hi, kSpecQB, SpecOut{spec, qexp, sat}, s_lo == 0);
     if (st != DDM_OK) return st;
     {
       ProfScope ps(p, DDM_KERNEL_TIME);
@@ -638,11 +676,13 @@ ddm_status ddm_structure_function(ddm_plan_t p, const void* frames, float* D) {
     }
     if (e != hipSuccess) return hip_fail(e, "time transform launch");
   }
-  if (p->f16) {
-    e = hipMemcpyAsync(p->sat_host, sat, sizeof(int32_t), hipMemcpyDeviceToHost, p->stream);
-    if (e == hipSuccess) e = hipEventRecord(p->sat_ev, p->stream);
-    if (e != hipSuccess) return hip_fail(e, "saturation count copy");
-    p->sat_pending = true;
+  if (readback) {
+    const int32_t* err = step_one_fused(p, fb, kSpecQB) ? step_one_ctl(p, inter) + step1_ctl_words(p->s1_maxslots) - 1
+                                                        : nullptr;
+    if (err != nullptr || sat != nullptr) {
+      e = rb_push(p, err, sat);
+      if (e != hipSuccess) return hip_fail(e, "readback copy");
+    }
   }
   return p->sat_total > 0 ? DDM_WARN_FP16_SATURATED : DDM_OK;
 }
@@ -651,8 +691,10 @@ ddm_status ddm_plan_fp16_saturations(ddm_plan_t p, int64_t* count) {
   ddm_status st = check_plan(p);
   if (st != DDM_OK) return st;
   if (count == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "count is NULL");
-  hipError_t e = sat_collect(p);
-  if (e != hipSuccess) return hip_fail(e, "saturation count");
+  if (p->rb_host != nullptr && !capturing(p)) {
+    hipError_t e = rb_collect(p, true);
+    if (e != hipSuccess) return hip_fail(e, "saturation count");
+  }
   *count = p->sat_total;
   return DDM_OK;
 }
@@ -667,7 +709,7 @@ ddm_status ddm_image_spectra(ddm_plan_t p, const void* frames, float* spectra) {
   const size_t fib = p->frame_inter_bytes;
   int fb = (int)std::min<size_t>(p->fb_target, std::max<size_t>(1, p->ws_bytes / fib));
   while (fb > 1 && (size_t)fb * fib > p->ws_bytes) --fb;
-  return run_step_one(p, frames, (float2*)p->ws, fb, 0, p->nq, 1, SpecOut{spectra, nullptr, nullptr});
+  return run_step_one(p, frames, (float2*)p->ws, fb, 0, p->nq, 1, SpecOut{spectra, nullptr, nullptr}, true);
 }
 
 ddm_status ddm_structure_from_spectra(ddm_plan_t p, const float* spectra, float* D) {

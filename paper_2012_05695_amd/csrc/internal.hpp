@@ -71,8 +71,10 @@ enum : int32_t {
 
 // ---- launchers (each returns hipSuccess or the launch error) ----
 // pack: slot 0 of every row carries R(0) + i R(W/2) (the Nyquist column is needed).
+// Frames t0 .. t0 + nframes - 1, or, when tsel (device, nframes entries) is not
+// NULL, frames tsel[0 .. nframes - 1]; intermediate frame z holds the z-th.
 hipError_t launch_row(hipStream_t s, int pixel, const void* frames, int W, int H, int64_t t0,
-                      int nframes, int precondition, float2* inter, int kxw, int pack,
+                      const int32_t* tsel, int nframes, int precondition, float2* inter, int kxw, int pack,
                       const float2* tw, int tws);
 
 // Destination of the column transform: complex FP32, or complex FP16 scaled
@@ -104,7 +106,8 @@ hipError_t launch_col(hipStream_t s, const float2* inter, int H, int kxw, int nt
 // frames W = H in {64, 128, 256, 512} with full column tiles.  ctl:
 // step1_ctl_words(maxslots) ints of device memory (initialised by the launch);
 // maxslots >= N + nwg / (items per frame) + 4; the last word is an error flag
-// (non-zero if a wait ran out).
+// (non-zero if a wait ran out), cleared by the launch when clear_err, else
+// kept from the previous launch (a later launch then does no work).
 bool step1_fusable(int W, int H, int ncol_tiles, int kxw);
 int step1_bufs();
 int step1_workgroups(int W);
@@ -112,7 +115,7 @@ __host__ __device__ size_t step1_ctl_words(int maxslots);
 hipError_t launch_step1(hipStream_t s, int pixel, const void* frames, int W, int N, int precondition,
                         float2* bufs, int kxw, int ntiles, int kxnyq, QTable qt, SlotMap sm, int64_t s_lo,
                         int64_t s_hi, SpecOut out, const float2* twW, const float2* twH, int* ctl, int maxslots,
-                        int nwg, int nbufs);
+                        int nwg, int nbufs, bool clear_err);
 
 hipError_t launch_qexp(hipStream_t s, const float2* pilot, int np, int64_t nq, int32_t* qexp);
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);

@@ -138,12 +138,15 @@ __device__ __forceinline__ void row_item(const PIX* __restrict__ frames, int H, 
 
 template <int W, int E, typename PIX>
 __global__ void __launch_bounds__(256) k_row(const PIX* __restrict__ frames, int H, int t0,
-                                             int precondition, float2* __restrict__ inter, int kxw,
-                                             int pack, const float2* __restrict__ tw, int tws) {
+                                             const int32_t* __restrict__ tsel, int precondition,
+                                             float2* __restrict__ inter, int kxw, int pack,
+                                             const float2* __restrict__ tw, int tws) {
   extern __shared__ float2 lds_row[];
   const int nt = blockDim.x / (W / E);
   const int ybase = blockIdx.x * nt * 2;
-  row_item<W, E, PIX>(frames, H, t0 + blockIdx.y, ybase, nt, precondition,
+  // frame t0 + z, or the z-th entry of the frame list
+  const int t = (tsel != nullptr) ? tsel[blockIdx.y] : t0 + (int)blockIdx.y;
+  row_item<W, E, PIX>(frames, H, t, ybase, nt, precondition,
                       inter + ((size_t)blockIdx.y * H + ybase) * kxw, kxw, pack, tw, tws, lds_row, threadIdx.x);
 }
 
@@ -508,21 +511,21 @@ ColCfg col_cfg(int H) {
 }
 
 template <int W, typename PIX>
-static hipError_t row_go(hipStream_t s, const void* frames, int H, int t0, int nframes,
+static hipError_t row_go(hipStream_t s, const void* frames, int H, int t0, const int32_t* tsel, int nframes,
                          int pre, float2* inter, int kxw, int pack, const float2* tw, int tws) {
   constexpr int E = (W % 3 == 0) ? 24 : 16;
   RowCfg c = row_cfg(W, H);
   dim3 grid(H / (2 * c.nt), nframes);
   hipLaunchKernelGGL((k_row<W, E, PIX>), grid, dim3(c.nt * c.T), c.lds, s,
-                     (const PIX*)frames, H, t0, pre, inter, kxw, pack, tw, tws);
+                     (const PIX*)frames, H, t0, tsel, pre, inter, kxw, pack, tw, tws);
   return hipGetLastError();
 }
 
 template <typename PIX>
-static hipError_t row_dispatch(hipStream_t s, const void* f, int W, int H, int t0, int nf, int pre,
-                               float2* inter, int kxw, int pack, const float2* tw, int tws) {
+static hipError_t row_dispatch(hipStream_t s, const void* f, int W, int H, int t0, const int32_t* tsel, int nf,
+                               int pre, float2* inter, int kxw, int pack, const float2* tw, int tws) {
   switch (W) {
-#define ROW_CASE(n) case n: return row_go<n, PIX>(s, f, H, t0, nf, pre, inter, kxw, pack, tw, tws);
+#define ROW_CASE(n) case n: return row_go<n, PIX>(s, f, H, t0, tsel, nf, pre, inter, kxw, pack, tw, tws);
     ROW_CASE(16) ROW_CASE(32) ROW_CASE(64) ROW_CASE(128) ROW_CASE(256) ROW_CASE(512)
     ROW_CASE(1024) ROW_CASE(2048) ROW_CASE(4096)
     ROW_CASE(48) ROW_CASE(96) ROW_CASE(192) ROW_CASE(384) ROW_CASE(768) ROW_CASE(1536) ROW_CASE(3072)
@@ -533,11 +536,13 @@ static hipError_t row_dispatch(hipStream_t s, const void* f, int W, int H, int t
 }
 
 hipError_t launch_row(hipStream_t s, int pixel, const void* frames, int W, int H, int64_t t0,
-                      int nframes, int precondition, float2* inter, int kxw, int pack, const float2* tw,
-                      int tws) {
+                      const int32_t* tsel, int nframes, int precondition, float2* inter, int kxw, int pack,
+                      const float2* tw, int tws) {
   if (pixel == DDM_PIX_U8)
-    return row_dispatch<uint8_t>(s, frames, W, H, (int)t0, nframes, precondition, inter, kxw, pack, tw, tws);
-  return row_dispatch<uint16_t>(s, frames, W, H, (int)t0, nframes, precondition, inter, kxw, pack, tw, tws);
+    return row_dispatch<uint8_t>(s, frames, W, H, (int)t0, tsel, nframes, precondition, inter, kxw, pack, tw,
+                                 tws);
+  return row_dispatch<uint16_t>(s, frames, W, H, (int)t0, tsel, nframes, precondition, inter, kxw, pack, tw,
+                                tws);
 }
 
 template <int H>
@@ -598,9 +603,10 @@ bool step1_fusable(int W, int H, int ncol_tiles, int kxw) {
 }
 
 // control words: per XCD [ticket, fidx[maxslots] = kUnset, rows[maxslots], cols[maxslots]], then
-// the global frame counter and the error flag, all 0 except fidx
-__global__ void k_step1_init(int* ctl, int maxslots) {
-  const int64_t total = (int64_t)step1_ctl_words(maxslots);
+// the global frame counter and the error flag, all 0 except fidx (the error
+// flag is left as it is unless clear_err)
+__global__ void k_step1_init(int* ctl, int maxslots, int clear_err) {
+  const int64_t total = (int64_t)step1_ctl_words(maxslots) - (clear_err ? 0 : 1);
   const int64_t per = 1 + 3 * (int64_t)maxslots;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t o = i % per;
@@ -634,9 +640,9 @@ int step1_workgroups(int W) {
 hipError_t launch_step1(hipStream_t s, int pixel, const void* frames, int W, int N, int precondition,
                         float2* bufs, int kxw, int ntiles, int kxnyq, QTable qt, SlotMap sm, int64_t s_lo,
                         int64_t s_hi, SpecOut out, const float2* twW, const float2* twH, int* ctl, int maxslots,
-                        int nwg, int nbufs) {
+                        int nwg, int nbufs, bool clear_err) {
   if (nbufs < 2) return hipErrorInvalidValue;  // a row item would wait on a later ticket
-  hipLaunchKernelGGL(k_step1_init, dim3(64), dim3(256), 0, s, ctl, maxslots);
+  hipLaunchKernelGGL(k_step1_init, dim3(64), dim3(256), 0, s, ctl, maxslots, clear_err ? 1 : 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int pack = kxnyq > 0, lo = (int)s_lo, hi = (int)s_hi;

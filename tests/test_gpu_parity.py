@@ -309,3 +309,19 @@ def test_fp16_paper_config_sampled(gpu):
     say("paper f16 sampled:", describe(e))
     assert e.max() <= TOL_F16
     assert plan.fp16_saturations() == 0
+
+
+def test_fp16_saturation_count_over_many_calls(gpu):
+    say("case: FP16 saturation counts of calls in flight")
+    # more calls than the host keeps in flight before it waits: every call's
+    # count is folded in exactly once
+    frames = synth.uniform_stack(64, 64, 1, seed=2).repeat(64, 1, 1)
+    frames[5] = 4095
+    frames = frames.cuda()
+    plan = gpu.Plan(64, 64, 64, spectrum="f16")
+    plan.structure_function(frames)
+    one = plan.fp16_saturations()
+    assert one > 0
+    for _ in range(9):
+        plan.structure_function(frames)
+    assert plan.fp16_saturations() == 10 * one
