@@ -931,7 +931,7 @@ ddm_status ddm_plan_autotune(ddm_plan_t p, int32_t* E_out, int32_t* qpw_out, dou
       for (int qpw : {1, 2, 4, 8, 16}) {
         if (e != hipSuccess) break;
         if (p->L / E < 1 || p->L % E != 0 || (E == 8 && p->L < 512)) continue;
-        if (qpw * (p->L / E) > 1024 || (size_t)qpw * (2 * p->L + p->L / 8 + 1) * 8 > 160 * 1024) continue;
+        if (qpw * (p->L / E) > 1024 || time_lds_bytes(p->L, qpw) > 160 * 1024) continue;
         const TimeShape sh{E, qpw};
         e = launch_time(p->stream, spec, kSpecQB, nq_t, p->N, p->M, p->twT, p->ramp, nullptr, qexp, dout, sh);
         if (e == hipSuccess) e = hipEventRecord(a, p->stream);
