@@ -7,13 +7,15 @@
 // contiguous kx interval [lo, hi); it is found with integer arithmetic only,
 // which makes bin membership bit-exact.
 //
-// One workgroup per (bin, 64-lag tile).  The bin's rows are taken in chunks
-// of 256; the members of a chunk are flattened, in q order, into an LDS list
-// (q index and weight), a window of kListCap entries at a time.  Wave w of the
-// four sums the entries j = w (mod 4) of each window for its 64 lags in FP64,
-// with 16 loads in flight, and the four partials are added in wave order at
-// the end: a fixed order that depends neither on the launch geometry nor on
-// timing, so results are deterministic.
+// One workgroup per (bin, tile of 64 LPT lags); each lane owns LPT
+// consecutive lags (LPT = 4 when rows of D are 16-byte aligned, so that a
+// wave reads 1 KiB of a row at once; else 1).  The bin's rows are taken in
+// chunks of 256; the members of a chunk are flattened, in q order, into an
+// LDS list (q index and weight), a window of kListCap entries at a time.
+// Wave w of the four sums the entries j = w (mod 4) of each window for its
+// lags in FP64, with 16 loads in flight, and the four partials are added in
+// wave order at the end: a fixed order that depends neither on the launch
+// geometry (LPT included) nor on timing, so results are deterministic.
 #include "internal.hpp"
 
 namespace ddm {
@@ -24,6 +26,21 @@ constexpr int kRadLags = 64;
 constexpr int kListCap = 4096;
 constexpr int kUnroll = 16;
 }  // namespace
+
+// LPT consecutive values of one row of D: one 16-byte load for 4 (the
+// address is 16-byte aligned), a plain load for 1.
+template <int LPT> struct Lags;
+template <> struct Lags<1> {
+  float v[1];
+  __device__ __forceinline__ static Lags load(const float* p) { return Lags{{*p}}; }
+};
+template <> struct Lags<4> {
+  float v[4];
+  __device__ __forceinline__ static Lags load(const float* p) {
+    const float4 f = *reinterpret_cast<const float4*>(p);
+    return Lags{{f.x, f.y, f.z, f.w}};
+  }
+};
 
 // smallest kx in [0, cnt) with kx^2 * a >= r (a > 0), or cnt if none; exact
 // integer result (the floating-point root is only a starting guess).
@@ -37,6 +54,7 @@ __device__ __forceinline__ int64_t first_kx(int64_t r, int64_t a, int64_t cnt) {
   return x;
 }
 
+template <int LPT>
 __global__ void __launch_bounds__(kRadThreads) k_radial(const float* __restrict__ D, int M, int W, int H,
                                                         int64_t ca, int64_t cc,
                                                         const int32_t* __restrict__ qoff,
@@ -48,8 +66,8 @@ __global__ void __launch_bounds__(kRadThreads) k_radial(const float* __restrict_
   const int b = blockIdx.x;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int m = blockIdx.y * kRadLags + lane;
-  const bool lag_ok = m < M;
+  const int m = (blockIdx.y * kRadLags + lane) * LPT;  // first of this lane's lags
+  const bool lag_ok = m < M;  // LPT = 4: M % 4 == 0, so all four are lags
   const bool write_bins = bin_of_q != nullptr && blockIdx.y == 0;
   const int64_t lo_t = thr[b], hi_t = thr[b + 1];
   const int half = W / 2;
@@ -59,10 +77,12 @@ __global__ void __launch_bounds__(kRadThreads) k_radial(const float* __restrict_
   __shared__ int32_t row_off[kRadThreads + 1];
   __shared__ int32_t wpart[4];
   __shared__ uint32_t list[kListCap];      // q | (weight 2) << 31
-  __shared__ double part[4][kRadLags];
+  __shared__ double part[4][kRadLags * LPT];
   __shared__ int64_t wpart64[4];
 
-  double acc = 0.0;
+  double acc[LPT];
+#pragma unroll
+  for (int i = 0; i < LPT; ++i) acc[i] = 0.0;
   int64_t wsum = 0;
   const float* Dm = D + m;
   for (int ky0 = 0; ky0 < H; ky0 += kRadThreads) {
@@ -120,34 +140,43 @@ __global__ void __launch_bounds__(kRadThreads) k_radial(const float* __restrict_
       if (lag_ok) {
         int j = wave;
         for (; j + 4 * (kUnroll - 1) < n; j += 4 * kUnroll) {
-          float v[kUnroll];
+          Lags<LPT> v[kUnroll];
           uint32_t e[kUnroll];
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u) {
             e[u] = list[j + 4 * u];
-            v[u] = Dm[(size_t)(e[u] & 0x7FFFFFFFu) * (size_t)M];
+            v[u] = Lags<LPT>::load(Dm + (size_t)(e[u] & 0x7FFFFFFFu) * (size_t)M);
           }
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) acc += ((e[u] >> 31) ? 2.0 : 1.0) * (double)v[u];
+          for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+            for (int i = 0; i < LPT; ++i) acc[i] += ((e[u] >> 31) ? 2.0 : 1.0) * (double)v[u].v[i];
         }
         for (; j < n; j += 4) {
           const uint32_t e = list[j];
-          acc += ((e >> 31) ? 2.0 : 1.0) * (double)Dm[(size_t)(e & 0x7FFFFFFFu) * (size_t)M];
+          const Lags<LPT> v = Lags<LPT>::load(Dm + (size_t)(e & 0x7FFFFFFFu) * (size_t)M);
+#pragma unroll
+          for (int i = 0; i < LPT; ++i) acc[i] += ((e >> 31) ? 2.0 : 1.0) * (double)v.v[i];
         }
       }
       __syncthreads();  // list[] is rewritten by the next window
     }
   }
   // partials of the four waves, added in wave order; weight sum over threads
-  part[wave][lane] = acc;
+#pragma unroll
+  for (int i = 0; i < LPT; ++i) part[wave][lane * LPT + i] = acc[i];
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) wsum += __shfl_xor(wsum, d, 64);
   if (lane == 0) wpart64[wave] = wsum;
   __syncthreads();
   if (wave == 0) {
     const int64_t ws = wpart64[0] + wpart64[1] + wpart64[2] + wpart64[3];
-    const double sum = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
-    if (lag_ok) Dbar[(size_t)b * M + m] = (ws > 0) ? sum / (double)ws : 0.0;
+#pragma unroll
+    for (int i = 0; i < LPT; ++i) {
+      const int c = lane * LPT + i;
+      const double sum = ((part[0][c] + part[1][c]) + part[2][c]) + part[3][c];
+      if (lag_ok) Dbar[(size_t)b * M + m + i] = (ws > 0) ? sum / (double)ws : 0.0;
+    }
     if (blockIdx.y == 0 && lane == 0) counts[b] = ws;
   }
 }
@@ -166,9 +195,15 @@ hipError_t launch_radial(hipStream_t s, const float* D, int64_t nq, int M, int W
     if (e != hipSuccess) return e;
   }
   if (nbins == 0) return hipSuccess;
-  dim3 grid(nbins, (M + kRadLags - 1) / kRadLags);
-  hipLaunchKernelGGL(k_radial, grid, dim3(kRadThreads), 0, s, D, M, W, H, ca, cc, qt.qoff, qt.kxcnt, thr,
-                     Dbar, counts, bin_of_q);
+  if (M % 4 == 0 && ((uintptr_t)D & 15) == 0) {
+    dim3 grid(nbins, (M / 4 + kRadLags - 1) / kRadLags);
+    hipLaunchKernelGGL(k_radial<4>, grid, dim3(kRadThreads), 0, s, D, M, W, H, ca, cc, qt.qoff, qt.kxcnt, thr,
+                       Dbar, counts, bin_of_q);
+  } else {
+    dim3 grid(nbins, (M + kRadLags - 1) / kRadLags);
+    hipLaunchKernelGGL(k_radial<1>, grid, dim3(kRadThreads), 0, s, D, M, W, H, ca, cc, qt.qoff, qt.kxcnt, thr,
+                       Dbar, counts, bin_of_q);
+  }
   return hipGetLastError();
 }
 

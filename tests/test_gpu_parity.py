@@ -187,6 +187,32 @@ def test_radial_wide_bins_and_threshold_reuse(gpu):
             assert torch.equal(Dbar, first)
 
 
+def test_radial_four_lag_lanes_match_one_lag_lanes(gpu):
+    """Rows of D 16-byte aligned with M % 4 == 0 take four lags per lane; the
+    same values one float off that alignment take one lag per lane: the
+    summation order is the same, so the results are bit-identical."""
+    say("case: radial lanes of 4 vs 1 lag, 96x96x64")
+    W = H = 96
+    frames = synth.uniform_stack(W, H, 64, seed=13, pixel="u8")
+    plan, Dg = run_full(gpu, frames)
+    kx, ky = plan.q_index()
+    k2max = int(dft.k2_of(kx, ky, W, H).max())
+    T = np.array([0, 1, 50, 51, 700, k2max + 1], dtype=np.int64)
+    D = torch.from_numpy(Dg).cuda()
+    buf = torch.empty(D.numel() + 1, dtype=torch.float32, device=D.device)
+    Dmis = buf[1:].view(D.shape)
+    Dmis.copy_(D)
+    assert D.data_ptr() % 16 == 0 and Dmis.data_ptr() % 16 == 4
+    a = plan.radial_average(D, T)
+    b = plan.radial_average(Dmis, T)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    Do_bar, Do_counts, _ = radial.radial_average(Dg.astype(np.float64), kx, ky, W, H, T)
+    np.testing.assert_array_equal(a[1].cpu().numpy(), Do_counts)
+    np.testing.assert_allclose(a[0].cpu().numpy(), Do_bar, rtol=1e-12, atol=0)
+
+
 @pytest.mark.parametrize("W,N,pixel,kw", [(64, 200, "u8", {}), (256, 96, "u16", {}), (512, 40, "u16", {}),
                                           (128, 64, "u16", {"k2_max": 900}),
                                           (256, 48, "u16", {"spectrum": "f16"})])
