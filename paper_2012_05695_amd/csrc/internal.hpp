@@ -27,10 +27,10 @@ struct TimeCfg {
 };
 TimeCfg time_cfg(int L);
 // Static LDS of the time kernel with qpw wave vectors per workgroup: staging
-// and exchange buffers per wave vector, the L-entry twiddle table, and room
-// for the reduction scratch.
+// and exchange buffers per wave vector, the L-entry twiddle table (L <= 1024),
+// and room for the reduction scratch.
 constexpr size_t time_lds_bytes(int L, int qpw) {
-  return (size_t)qpw * (2 * (size_t)L + L / 8 + 1) * 8 + (size_t)L * 8 + 1024;
+  return (size_t)qpw * (2 * (size_t)L + L / 8 + 1) * 8 + (L <= 1024 ? (size_t)L * 8 : 8) + 1024;
 }
 
 struct RowCfg {

@@ -147,9 +147,14 @@ __device__ __forceinline__ int64_t time_q0(int64_t id) {
 // F16 (blocked store only): complex FP16 scaled by 2^qexp[q], unscaled on load
 // (exact: a power of two).
 //
-// Persistent: workgroup b takes groups b, b + gridDim.x, ...; the loads of
-// the next group are issued before the transforms of the current one and
-// land in registers while they run.
+// Workgroup b takes groups b, b + gridDim.x, ...  For L <= 1024 the grid is
+// persistent and the loads of the next group are issued before the
+// transforms of the current one, landing in registers while they run; longer
+// transforms have no registers to spare for that (one wave per SIMD instead
+// of two) and take one group per workgroup, loaded when it starts.
+template <int L>
+constexpr bool time_prefetch() { return L <= 1024; }
+
 template <int L, int QPW, int QB, int E, bool FULL, bool F16>
 __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__ spec, int64_t nq,
                                                        int N, int M, const float2* __restrict__ twN2,
@@ -166,7 +171,10 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
   constexpr uint32_t ES = F16 ? 4u : 8u;    // bytes per stored complex value
   __shared__ float2 xall[QPW * XS];
   __shared__ float2 yall[QPW * YS];
-  __shared__ float2 wtab[L];  // e^{-2 pi i n / N2}, n < L
+  constexpr bool PF = time_prefetch<L>();
+  // e^{-2 pi i n / N2}, n < L, where the group loop prefetches (its global
+  // loads would wait for the prefetch); read from the table otherwise
+  __shared__ float2 wtab[PF ? L : 1];
   __shared__ double red[QPW * (T > 64 ? T / 64 : 1)];
   __shared__ float redf[QPW * (T > 64 ? T / 64 : 1)];
   if (FULL && (N != L || M != L)) return;  // guarded by the launcher; uniform
@@ -178,7 +186,9 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
   // registers and shared by the three transforms of every wave vector
   TwCache<L, E> tc;
   tc.load(threadIdx.x % T, [&](int j) { return ld_f2(tw_r, (uint32_t)(2 * j) * 8u); });
-  for (int j = threadIdx.x; j < L; j += NT) wtab[j] = ld_f2(tw_r, (uint32_t)j * 8u);
+  if constexpr (PF)
+    for (int j = threadIdx.x; j < L; j += NT) wtab[j] = ld_f2(tw_r, (uint32_t)j * 8u);
+  auto w_n = [&](int n) { return PF ? wtab[n] : ld_f2(tw_r, (uint32_t)n * 8u); };
 
   // This thread's share of a group's input: element f = threadIdx.x + r NT of
   // the group's QPW sequences (raw: FP32 pairs, or the FP16 pair's bits in .x).
@@ -214,7 +224,7 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
   };
 
   int64_t id = blockIdx.x;
-  if (id < nids && time_q0<QPW, QB>(id) < nq) issue_loads(time_q0<QPW, QB>(id), threadIdx.x);
+  if (PF && id < nids && time_q0<QPW, QB>(id) < nq) issue_loads(time_q0<QPW, QB>(id), threadIdx.x);
   for (; id < nids; id += gridDim.x) {
     // the thread index, made opaque per group so that the per-thread LDS
     // addresses of the whole group are not hoisted out of the loop (they
@@ -225,11 +235,12 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
     const int tid = tx % T;
     const int64_t q0 = time_q0<QPW, QB>(id);
     const int64_t nid = id + gridDim.x;
-    const bool next = nid < nids && time_q0<QPW, QB>(nid) < nq;
+    const bool next = PF && nid < nids && time_q0<QPW, QB>(nid) < nq;
     if (q0 >= nq) {  // uniform: a padding id
       if (next) issue_loads(time_q0<QPW, QB>(nid), tx);
       continue;
     }
+    if (!PF) issue_loads(q0, tx);
     __syncthreads();  // every wave is done with the previous group's LDS data
 
     // ---- stage the QPW sequences in LDS, [q][t] ----
@@ -298,7 +309,7 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int n = tid + e * T;
-      v[e] = cmul(xp(xb[n], n), wtab[n]);
+      v[e] = cmul(xp(xb[n], n), w_n(n));
     }
     fft_forward_c<L, E, 1, true, WAVE>(v, yb, tid, tc);
     float po[E];
@@ -373,7 +384,7 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
         if (FULL || m < M) {
           const float2 zm = v[e];
           const float2 zr = yb[(L - m) & (L - 1)];
-          const float2 w = wtab[m];  // (cos th, -sin th), th = 2 pi m / N2
+          const float2 w = w_n(m);  // (cos th, -sin th), th = 2 pi m / N2
           // 2 Re c(m) = (2/N2) Re sum_k P_k e^{2 pi i k m / N2}
           const float two_c = 0.5f * ((zm.x + zr.x) + w.x * (zm.y + zr.y) - w.y * (zm.x - zr.x)) * inv_l;
           const double num = (xd[LdsView<1, true>::slot(N - m)] + sN) - xd[LdsView<1, true>::slot(m)] -
@@ -447,14 +458,15 @@ static int64_t resident_wgs(K kernel, int block) {
   return (int64_t)per_cu * device_cus();
 }
 
-// Grid of the persistent time kernel: at most the resident workgroups, a
-// multiple of 8 (so that every workgroup keeps to one XCD's ids), at most one
-// workgroup per id.
+// Grid of the time kernel: one workgroup per id, or, where it prefetches, at
+// most the resident workgroups, a multiple of 8 (so that every workgroup
+// keeps to one XCD's ids).
 template <int L, int QPW, int QB, int E, bool FULL, bool F16>
 static void time_launch_one(hipStream_t s, int64_t nids, dim3 block, const void* spec, int64_t nq, int N, int M,
                             const float2* tw, const double* ramp, const int32_t* qmap, const int32_t* qexp,
                             float* D) {
-  static const int64_t res = resident_wgs(k_time<L, QPW, QB, E, FULL, F16>, (int)block.x);
+  static const int64_t res =
+      time_prefetch<L>() ? resident_wgs(k_time<L, QPW, QB, E, FULL, F16>, (int)block.x) : INT64_MAX;
   int64_t g = res >= 8 ? res / 8 * 8 : res;
   if (g > nids) g = nids;
   hipLaunchKernelGGL((k_time<L, QPW, QB, E, FULL, F16>), dim3((unsigned)g), block, 0, s, spec, nq, N, M, tw, ramp,
