@@ -413,8 +413,11 @@ __global__ void __launch_bounds__(16 * (W / E)) k_step1(const PIX* __restrict__ 
     // the thread index, made opaque per item so that the per-thread addresses
     // of both item kinds are not hoisted out of the loop (they would all stay
     // live in registers)
-    int tx = threadIdx.x;
-    asm volatile("" : "+v"(tx));
+    // (the mask restores its range, the workgroup size being a power of two)
+    static_assert(((16 * (W / E)) & (16 * (W / E) - 1)) == 0, "workgroup size is a power of two");
+    unsigned utx = threadIdx.x;
+    asm volatile("" : "+v"(utx));
+    const int tx = (int)(utx & (unsigned)(16 * (W / E) - 1));
     if (is_row) {
       // the buffer is free once the columns of the slot that last used it
       // have read it (that slot has a frame: claims are in slot order)
