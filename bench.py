@@ -81,7 +81,7 @@ def time_flops(N, M):
 
 
 # sources each profiled kernel is built from (a summary is valid while they hash the same)
-PROFILED_SOURCES = {"k_time": ("k_time.hip", "fft.hpp", "internal.hpp"),
+PROFILED_SOURCES = {"k_time": ("time_kernel.hpp", "fft.hpp", "internal.hpp"),
                     "k_step1": ("k_spatial.hip", "fft.hpp", "internal.hpp")}
 
 

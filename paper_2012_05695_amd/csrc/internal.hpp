@@ -17,15 +17,6 @@ namespace ddm {
 // the time transform.
 constexpr int kSpecQB = 16;
 
-// Launch geometry of the time-stage kernel for a given padded length L.
-struct TimeCfg {
-  int L;      // half of the zero-padded length N2 (power of two, >= 16)
-  int E;      // complex values per thread
-  int T;      // threads per wave vector (L / E)
-  int qpw;    // wave vectors per workgroup
-  size_t lds; // dynamic LDS bytes
-};
-TimeCfg time_cfg(int L);
 // Static LDS of the time kernel with qpw wave vectors per workgroup: staging
 // and exchange buffers per wave vector, the L-entry twiddle table (L <= 1024),
 // and room for the reduction scratch.
