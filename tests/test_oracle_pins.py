@@ -191,34 +191,35 @@ def test_weighted_sum_rule_exact_integer():
         assert abs(lhs - num / den) <= 1e-12 * max(1.0, num / den)
 
 
-# -------------------------------------------- the paper's method (App. B) ---
+# ------------------------------------ the Fourier route of Eq. (2) / App. B ---
 
-def appendix_b(F):
-    """Structure function of one time sequence by the steps of Appendix B,
-    written here independently with a library FFT, FP64:
-    zero-pad to N2 (Eq. B4), FFT, squared modulus, inverse FFT, real part of
-    the first N entries times 1/(N-m) -> d_c (with its factor 2, Eq. B2);
-    d_a by the recursion Eq. (B3); d = d_a - d_c."""
+def fourier_route(F):
+    """D of one time sequence through the Fourier route, derived from the
+    algebra rather than from the paper's procedure.  Expanding
+    |F_n - F_{n-m}|^2 = |F_n|^2 + |F_{n-m}|^2 - 2 Re(conj(F_{n-m}) F_n)
+    splits the sum of Eq. (1) into prefix sums S(k) = sum_{j<k} |F_j|^2 and the
+    acyclic autocorrelation c(m) = sum_{n=m}^{N-1} conj(F_{n-m}) F_n.  A cyclic
+    correlation of length P >= 2N - 1 has no wrap-around terms, so it equals
+    the acyclic one, and by the correlation theorem it is the inverse DFT of
+    |DFT(F zero-padded to P)|^2.  P = 2N - 1 here (not a power of two), with a
+    library FFT, FP64."""
     N = len(F)
-    N2 = 2 ** (math.ceil(math.log2(N)) + 1)
-    X = np.fft.fft(np.concatenate([F, np.zeros(N2 - N)]))
-    r = np.fft.ifft(np.abs(X) ** 2)[:N].real
+    X = np.fft.fft(F, n=2 * N - 1)
+    c = np.fft.ifft(X * np.conj(X))[:N].real
+    S = np.concatenate([[0.0], np.cumsum(np.abs(F) ** 2)])
     m = np.arange(N)
-    d_c = 2.0 * r / (N - m)
-    a = np.abs(F) ** 2
-    d_a = np.zeros(N + 1)
-    for n in range(N):  # d_a(N-n-1) = n/(n+1) d_a(N-n) + (|F_n|^2 + |F_{N-n-1}|^2)/(n+1)
-        d_a[N - n - 1] = n / (n + 1) * d_a[N - n] + (a[n] + a[N - n - 1]) / (n + 1)
-    return d_a[:N] - d_c
+    return (S[N] - S[m] + S[N - m] - 2.0 * c) / (N - m)
 
 
 @pytest.mark.parametrize("N", [2, 3, 5, 128, 1000])
-def test_direct_difference_equals_paper_method(N):
+def test_direct_difference_equals_fourier_route(N):
+    """The method's exactness claim (Appendix B: the zero-padded transform gives
+    Eq. (1) exactly): the oracle's direct differences equal the Fourier route."""
     r = rng(13 + N)
     F = r.standard_normal((6, N)) + 1j * r.standard_normal((6, N)) + 3.0
     D = structure.structure_function_direct(F, impl="numpy")
     for q in range(F.shape[0]):
-        ref = appendix_b(F[q])
+        ref = fourier_route(F[q])
         np.testing.assert_allclose(D[q], ref, rtol=0, atol=1e-12 * np.abs(ref).max() + 1e-14)
 
 
