@@ -77,7 +77,7 @@ def test_step_one_spectra(gpu, precondition):
     assert err < 2e-6
 
 
-@pytest.mark.parametrize("N", [2, 3, 5, 17, 100, 1000, 1537, 4096])
+@pytest.mark.parametrize("N", [2, 3, 5, 17, 100, 1000, 1537, 2048, 3000, 4096])
 def test_step_two_from_spectra(gpu, N):
     say("case: step two N =", N)
     r = np.random.default_rng(N)
