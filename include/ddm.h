@@ -131,6 +131,24 @@ ddm_status ddm_plan_set_workspace(ddm_plan_t plan, void* workspace_dev, size_t b
  * is not valid).  Calls made inside a HIP graph capture hand nothing back. */
 ddm_status ddm_structure_function(ddm_plan_t plan, const void* frames_dev, float* D_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as ddm_structure_function, bit for bit, with the library's own
+ * static device scratch of DDM_NOALLOC_SCRATCH_BYTES (256 MiB, held by each
+ * device the library runs on from module load to process end) as the
+ * workspace instead of the attached one (which is neither needed nor
+ * touched).  The caller passes frames and D as for ddm_structure_function.
+ * Plans whose minimum workspace (ddm_plan_workspace_size) exceeds the scratch
+ * return DDM_ERR_UNSUPPORTED; a plan whose full workspace exceeds it runs in
+ * groups (every frame transformed once per group).  The call allocates no
+ * device or host memory (the scratch address is looked up once per device,
+ * on that device's first call).  Every call on a device uses the same
+ * scratch, which keeps the last call's contents: calls that overlap on one
+ * device (different streams, or different threads) race and give invalid
+ * results; calls on one stream are ordered and safe. */
+#define DDM_NOALLOC_SCRATCH_BYTES (256u << 20)
+ddm_status ddm_structure_function_noalloc(ddm_plan_t plan, const void* frames_dev, float* D_dev);
+
 /* FP16 spectrum store: total number of spectrum components clipped to
  * +-65504 since the plan was created (waits for every call enqueued so far). */
 ddm_status ddm_plan_fp16_saturations(ddm_plan_t plan, int64_t* count);

@@ -32,6 +32,8 @@ DDM_KERNEL_TIME = 4
 DDM_KERNEL_RADIAL = 8
 DDM_KERNEL_STEP1 = 16
 
+DDM_NOALLOC_SCRATCH_BYTES = 256 << 20  # static device scratch of ddm_structure_function_noalloc
+
 DDM_PIX_U8 = 1
 DDM_PIX_U16 = 2
 DDM_SPEC_F32 = 0
@@ -95,6 +97,7 @@ SIGNATURES = [
     ("ddm_plan_workspace_size", c_int32, [c_void_p, P(c_size_t), P(c_size_t)]),
     ("ddm_plan_set_workspace", c_int32, [c_void_p, c_void_p, c_size_t]),
     ("ddm_structure_function", c_int32, [c_void_p, c_void_p, c_void_p]),
+    ("ddm_structure_function_noalloc", c_int32, [c_void_p, c_void_p, c_void_p]),
     ("ddm_image_spectra", c_int32, [c_void_p, c_void_p, c_void_p]),
     ("ddm_structure_from_spectra", c_int32, [c_void_p, c_void_p, c_void_p]),
     ("ddm_radial_average", c_int32,

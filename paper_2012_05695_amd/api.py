@@ -38,6 +38,8 @@ def abi_version():
     return int(_lib.ddm_abi_version())
 
 
+NOALLOC_SCRATCH_BYTES = L.DDM_NOALLOC_SCRATCH_BYTES
+
 _PIX = {"u8": L.DDM_PIX_U8, "u16": L.DDM_PIX_U16}
 _PIX_DTYPES = {L.DDM_PIX_U8: (torch.uint8,), L.DDM_PIX_U16: (torch.uint16, torch.int16)}
 _SPEC = {"f32": L.DDM_SPEC_F32, "f16": L.DDM_SPEC_F16_QSCALED}
@@ -188,6 +190,19 @@ class Plan:
         with torch.cuda.device(self.device):
             self.last_status = _check(_lib.ddm_structure_function(self._h, ctypes.c_void_p(frames.data_ptr()),
                                                                   ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def structure_function_noalloc(self, frames, out=None):
+        """As structure_function, on the library's static device scratch instead
+        of a workspace (ddm_structure_function_noalloc): no device allocation
+        in the call when `out` is given."""
+        self._frames_ok(frames)
+        if out is None:
+            out = torch.empty((self.n_q, self.max_lag), dtype=torch.float32, device=frames.device)
+        _require(out, "D", (torch.float32,), (self.n_q, self.max_lag), self.device)
+        with torch.cuda.device(self.device):
+            self.last_status = _check(_lib.ddm_structure_function_noalloc(
+                self._h, ctypes.c_void_p(frames.data_ptr()), ctypes.c_void_p(out.data_ptr())))
         return out
 
     def fp16_saturations(self):

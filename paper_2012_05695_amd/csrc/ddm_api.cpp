@@ -631,12 +631,9 @@ static bool capturing(const ddm_plan_s* p) {
   return hipStreamIsCapturing(p->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
 }
 
-ddm_status ddm_structure_function(ddm_plan_t p, const void* frames, float* D) {
-  ddm_status st = check_plan(p);
-  if (st != DDM_OK) return st;
-  if (frames == nullptr || D == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "frames/D is NULL");
-  if (((uintptr_t)frames & 15) != 0) return fail(DDM_ERR_INVALID_ARGUMENT, "frames must be 16-byte aligned");
-  if (p->ws == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "no workspace attached (ddm_plan_set_workspace)");
+// The whole path on the workspace p->ws (p->ws_bytes); arguments checked.
+static ddm_status structure_function_run(ddm_plan_s* p, const void* frames, float* D) {
+  ddm_status st;
   // nothing comes back from a call made inside a graph capture
   const bool readback = p->rb_host != nullptr && !capturing(p);
   hipError_t e;
@@ -685,6 +682,75 @@ ddm_status ddm_structure_function(ddm_plan_t p, const void* frames, float* D) {
     }
   }
   return p->sat_total > 0 ? DDM_WARN_FP16_SATURATED : DDM_OK;
+}
+
+static ddm_status check_sf_args(ddm_plan_t p, const void* frames, float* D) {
+  ddm_status st = check_plan(p);
+  if (st != DDM_OK) return st;
+  if (frames == nullptr || D == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "frames/D is NULL");
+  if (((uintptr_t)frames & 15) != 0) return fail(DDM_ERR_INVALID_ARGUMENT, "frames must be 16-byte aligned");
+  return DDM_OK;
+}
+
+ddm_status ddm_structure_function(ddm_plan_t p, const void* frames, float* D) {
+  ddm_status st = check_sf_args(p, frames, D);
+  if (st != DDM_OK) return st;
+  if (p->ws == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "no workspace attached (ddm_plan_set_workspace)");
+  return structure_function_run(p, frames, D);
+}
+
+// ---------------------------------------------------------------------------
+// The structure function on a workspace that the library holds in a static
+// device array, for callers that cannot allocate device memory.  Each device
+// holds its own copy of the array (from module load to process end); its
+// address on a device is looked up once, with that device current, and kept.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[DDM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];  // device address of `scratch` per device, or NULL before the lookup
+}  // namespace
+
+static ddm_status scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(DDM_ERR_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (ptr == nullptr || ((uintptr_t)ptr & 255) != 0)
+      return fail(DDM_ERR_HIP, "static scratch has no usable device address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return DDM_OK;
+}
+
+ddm_status ddm_structure_function_noalloc(ddm_plan_t p, const void* frames, float* D) {
+  ddm_status st = check_sf_args(p, frames, D);
+  if (st != DDM_OK) return st;
+  size_t mn = 0;
+  ddm_plan_workspace_size(p, &mn, nullptr);
+  if (mn > (size_t)DDM_NOALLOC_SCRATCH_BYTES)
+    return fail(DDM_ERR_UNSUPPORTED, "this plan needs at least %zu bytes of workspace; the static scratch holds %zu",
+                mn, (size_t)DDM_NOALLOC_SCRATCH_BYTES);
+  void* ptr = nullptr;
+  if ((st = scratch_address(&ptr)) != DDM_OK) return st;
+  // the call runs on the scratch in place of the attached workspace, which is
+  // left as it was
+  void* ws = p->ws;
+  const size_t ws_bytes = p->ws_bytes;
+  p->ws = ptr;
+  p->ws_bytes = DDM_NOALLOC_SCRATCH_BYTES;
+  st = structure_function_run(p, frames, D);
+  p->ws = ws;
+  p->ws_bytes = ws_bytes;
+  return st;
 }
 
 ddm_status ddm_plan_fp16_saturations(ddm_plan_t p, int64_t* count) {

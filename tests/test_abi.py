@@ -88,3 +88,11 @@ def test_host_only_calls(libddm_path):
     assert lib.ddm_plan_create(None, ctypes.byref(h)) == _lib.DDM_ERR_INVALID_ARGUMENT
     assert lib.ddm_plan_destroy(None) == _lib.DDM_OK
     assert lib.ddm_structure_function(None, None, None) == _lib.DDM_ERR_INVALID_ARGUMENT
+
+
+def test_noalloc_scratch_size_matches_header():
+    from paper_2012_05695_amd import _lib
+    text = open(os.path.join(ROOT, "include", "ddm.h")).read()
+    m = re.search(r"#define DDM_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert m, "DDM_NOALLOC_SCRATCH_BYTES not found"
+    assert int(m.group(1)) << int(m.group(2)) == _lib.DDM_NOALLOC_SCRATCH_BYTES
