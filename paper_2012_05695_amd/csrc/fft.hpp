@@ -148,6 +148,44 @@ template <bool WAVE> __device__ __forceinline__ void group_sync() {
   }
 }
 
+// LDS addressing of one Stockham pass.  Butterfly b of thread tid (j = tid +
+// b T) writes its k-th output to element (j / NS) NS R + (j mod NS) + k NS, and
+// the next pass reads element tid + e T.  For the power-of-two thread counts
+// used here every such slot (padding included) is the thread's first slot plus
+// an offset that depends only on (b, k) or e; the check below proves it for
+// every thread at compile time, and the pass then computes one base address per
+// thread and uses constant offsets (otherwise it evaluates each index).
+template <int L, int E, int R, int NS, bool PAD>
+struct PassLayout {
+  static constexpr int T = L / E;
+  static constexpr int NB = E / R;
+  static constexpr int sl(int i) { return PAD ? i + (i >> 4) : i; }
+  static constexpr int widx(int tid, int b, int k) {
+    return ((tid + b * T) / NS) * NS * R + (tid + b * T) % NS + k * NS;
+  }
+  static constexpr int woff(int b, int k) { return sl(widx(0, b, k)) - sl(widx(0, 0, 0)); }
+  static constexpr int roff(int e) { return sl(e * T) - sl(0); }
+  static constexpr bool check() {
+    for (int tid = 0; tid < T; ++tid) {
+      const int w0 = sl(widx(tid, 0, 0));
+      for (int b = 0; b < NB; ++b)
+        for (int k = 0; k < R; ++k)
+          if (sl(widx(tid, b, k)) - w0 != woff(b, k)) return false;
+      const int r0 = sl(tid);
+      for (int e = 0; e < E; ++e)
+        if (sl(tid + e * T) - r0 != roff(e)) return false;
+    }
+    return true;
+  }
+  static constexpr bool kLinear = ((T & (T - 1)) == 0) && ((NS & (NS - 1)) == 0) && check();
+  // first write slot and first read slot of thread tid (< T)
+  __device__ __forceinline__ static int wbase(unsigned tid) {
+    const unsigned i = (tid / (unsigned)NS) * (unsigned)(NS * R) + tid % (unsigned)NS;
+    return (int)(PAD ? i + (i >> 4) : i);
+  }
+  __device__ __forceinline__ static int rbase(unsigned tid) { return (int)(PAD ? tid + (tid >> 4) : tid); }
+};
+
 // Pass of radix R with span NS (product of the radices already applied).
 // Exchanges through LDS unless it is the last pass.  Every thread of the
 // workgroup must call it (it contains __syncthreads()).  twf(b, k, jm) gives
@@ -157,13 +195,17 @@ __device__ __forceinline__ void stockham_pass_g(float2 (&v)[E], LdsView<STR, PAD
   constexpr int T = L / E;
   constexpr int NB = E / R;
   constexpr bool LAST = (NS * R == L);
+  using PL = PassLayout<L, E, R, NS, PAD>;
+  const unsigned ut = (unsigned)tid;
+  float2* wp = nullptr;
+  if constexpr (!LAST && PL::kLinear) wp = buf.base + PL::wbase(ut) * STR;
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int j = tid + b * T;
     float2 x[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) x[k] = v[b + k * NB];
-    const int jm = (NS == 1) ? 0 : (j % NS);
+    // j mod NS of butterfly j = tid + b T (NS and T are powers of two, or NS = 1)
+    const int jm = (NS == 1) ? 0 : (int)((ut + (unsigned)(b * T)) % (unsigned)NS);
     if (NS > 1) {
 #pragma unroll
       for (int k = 1; k < R; ++k) x[k] = cmul(x[k], twf(b, k, jm));
@@ -172,7 +214,11 @@ __device__ __forceinline__ void stockham_pass_g(float2 (&v)[E], LdsView<STR, PAD
     if (LAST) {
 #pragma unroll
       for (int k = 0; k < R; ++k) v[b + k * NB] = x[k];
+    } else if constexpr (PL::kLinear) {
+#pragma unroll
+      for (int k = 0; k < R; ++k) wp[PL::woff(b, k) * STR] = x[k];
     } else {
+      const int j = tid + b * T;
       const int base = (j / NS) * NS * R + jm;
 #pragma unroll
       for (int k = 0; k < R; ++k) buf[base + k * NS] = x[k];
@@ -180,8 +226,14 @@ __device__ __forceinline__ void stockham_pass_g(float2 (&v)[E], LdsView<STR, PAD
   }
   if (!LAST) {
     group_sync<WAVE>();
+    if constexpr (PL::kLinear) {
+      const float2* rp = buf.base + PL::rbase(ut) * STR;
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = buf[tid + e * T];
+      for (int e = 0; e < E; ++e) v[e] = rp[PL::roff(e) * STR];
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = buf[tid + e * T];
+    }
     group_sync<WAVE>();
   }
 }

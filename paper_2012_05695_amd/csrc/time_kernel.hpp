@@ -169,6 +169,7 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
   constexpr int XS = lds_len<true>(L) + 1;  // staging stride (odd: spreads the transposed writes)
   constexpr int YS = lds_len<true>(L);      // exchange buffer stride
   constexpr int NT = QPW * T;
+  static_assert((T & (T - 1)) == 0, "threads per transform must be a power of two");
   constexpr uint32_t ES = F16 ? 4u : 8u;    // bytes per stored complex value
   __shared__ float2 xall[QPW * XS];
   __shared__ float2 yall[QPW * YS];
@@ -194,9 +195,12 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
   // This thread's share of a group's input: element f = threadIdx.x + r NT of
   // the group's QPW sequences (raw: FP32 pairs, or the FP16 pair's bits in .x).
   float2 ld[E];
+  // q0 < 0: no group (a range of 0 bytes: every load returns 0 and reads nothing)
   auto issue_loads = [&](int64_t q0, int tx) {
     __amdgpu_buffer_rsrc_t in_r;
-    if constexpr (QB == 1) {
+    if (q0 < 0) {
+      in_r = make_rsrc(spec, 0u);
+    } else if constexpr (QB == 1) {
       const int64_t nvalid = (nq - q0) < QPW ? (nq - q0) : QPW;
       in_r = make_rsrc((const float2*)spec + (size_t)q0 * N, (uint32_t)(nvalid * N * sizeof(float2)));
     } else {
@@ -206,6 +210,9 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
       in_r = make_rsrc((const char*)spec + ((size_t)blk * N * QB + sub) * ES,
                        (uint32_t)(((size_t)(N - 1) * QB + QPW) * ES));
     }
+    // blocked layout: element f = tx + r NT is time tx / QPW + r T of sequence
+    // tx % QPW, so its offset is a per-thread base plus a constant
+    const uint32_t off0 = ((uint32_t)tx / QPW * QB + (uint32_t)tx % QPW) * ES;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int f = tx + r * NT;
@@ -214,8 +221,7 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
         const int i = f / L, t = f % L;
         off = (FULL || t < N) ? (uint32_t)(i * N + t) * 8u : 0xFFFFFFF0u;
       } else {
-        const int t = f / QPW, i = f % QPW;
-        off = (uint32_t)(t * QB + i) * ES;
+        off = off0 + (uint32_t)(r * T * QB) * ES;
       }
       if constexpr (F16)
         ld[r].x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(in_r, off, 0, 0));
@@ -225,7 +231,7 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
   };
 
   int64_t id = blockIdx.x;
-  if (PF && id < nids && time_q0<QPW, QB>(id) < nq) issue_loads(time_q0<QPW, QB>(id), threadIdx.x);
+  if (PF) issue_loads((id < nids && time_q0<QPW, QB>(id) < nq) ? time_q0<QPW, QB>(id) : -1, threadIdx.x);
   for (; id < nids; id += gridDim.x) {
     // the thread index, made opaque per group so that the per-thread LDS
     // addresses of the whole group are not hoisted out of the loop (they
@@ -236,42 +242,51 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
     const int tid = tx % T;
     const int64_t q0 = time_q0<QPW, QB>(id);
     const int64_t nid = id + gridDim.x;
-    const bool next = PF && nid < nids && time_q0<QPW, QB>(nid) < nq;
-    if (q0 >= nq) {  // uniform: a padding id
-      if (next) issue_loads(time_q0<QPW, QB>(nid), tx);
-      continue;
+    // the next group's first slot, -1 for none (past the end or a padding id)
+    const int64_t q0n = (PF && nid < nids && time_q0<QPW, QB>(nid) < nq) ? time_q0<QPW, QB>(nid) : -1;
+    const bool live = q0 < nq;  // uniform: false for a padding id
+    if (!PF) {
+      if (!live) continue;
+      issue_loads(q0, tx);
     }
-    if (!PF) issue_loads(q0, tx);
     __syncthreads();  // every wave is done with the previous group's LDS data
 
     // ---- stage the QPW sequences in LDS, [q][t] ----
-    {
+    if (live) {
       float sc = 1.0f;  // 2^-qexp of this thread's wave vector (blocked layout: i = threadIdx.x % QPW)
       if constexpr (F16) {
         const int64_t ss = q0 + (tx % QPW);
         const int qq = (ss < nq) ? (qmap ? qmap[ss] : (int)ss) : -1;
         sc = (qq >= 0) ? ldexpf(1.0f, -qexp[qq]) : 1.0f;
       }
+      // blocked layout: time tx / QPW + r T of sequence tx % QPW; T is a power
+      // of two and tx / QPW < T, so the padded slot of that time is the slot of
+      // tx / QPW plus the slot of r T
+      float2* xs = xall + ((uint32_t)tx % QPW) * XS + LdsView<1, true>::slot((uint32_t)tx / QPW);
 #pragma unroll
       for (int r = 0; r < E; ++r) {
-        const int f = tx + r * NT;
-        int t, i;
-        if constexpr (QB == 1) { i = f / L; t = f % L; }
-        else { t = f / QPW; i = f % QPW; }
         float2 val = ld[r];
         if constexpr (F16) {
           const __half2 h = __builtin_bit_cast(__half2, __builtin_bit_cast(uint32_t, ld[r].x));
           val = make_float2(__low2float(h) * sc, __high2float(h) * sc);
         }
-        xall[i * XS + LdsView<1, true>::slot(t)] = val;
+        if constexpr (QB == 1) {
+          const int f = tx + r * NT;
+          xall[(f / L) * XS + LdsView<1, true>::slot(f % L)] = val;
+        } else {
+          xs[LdsView<1, true>::slot(r * T)] = val;
+        }
       }
     }
     __syncthreads();
 
+    // the next group's loads run during this group's transforms; issued on
+    // every path (also for no group), so that the registers they fill are the
+    // only values of `ld` that reach the next iteration
+    if (PF) issue_loads(q0n, tx);
+    if (!live) continue;
     const int64_t q = q0 + qi;  // slot of this wave vector in the store
     const int qd = (q < nq) ? (qmap ? qmap[q] : (int)q) : -1;  // its row of D (-1: a hole)
-    // the next group's loads run during this group's transforms
-    if (next) issue_loads(time_q0<QPW, QB>(nid), tx);
 
     LdsView<1, true> xb{xall + qi * XS};
     LdsView<1, true> yb{yall + qi * YS};
@@ -379,23 +394,33 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
       const double sN = xd[LdsView<1, true>::slot(N)];
       const float inv_l = 1.0f / (float)L;  // 2 / N2, exact
       float* drow = D + (size_t)qd * M;
+      // With T a multiple of 16, the padded slots of m = tid + e T, N - m and
+      // L - m (for e >= 1, where L - m >= 1) are a per-thread slot plus or
+      // minus the slot of e T.
+      constexpr bool LIN = (T % 16 == 0);
+      const int s_m = LdsView<1, true>::slot(tid);
+      const int s_nm = LdsView<1, true>::slot(N - tid);
+      const int s_lm = LdsView<1, true>::slot(L - tid);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int m = tid + e * T;
         if (FULL || m < M) {
+          const int set = LdsView<1, true>::slot(e * T);
           const float2 zm = v[e];
-          const float2 zr = yb[(L - m) & (L - 1)];
+          const float2 zr = (LIN && e > 0) ? yb.base[s_lm - set] : yb[(L - m) & (L - 1)];
           const float2 w = w_n(m);  // (cos th, -sin th), th = 2 pi m / N2
           // 2 Re c(m) = (2/N2) Re sum_k P_k e^{2 pi i k m / N2}
           const float two_c = 0.5f * ((zm.x + zr.x) + w.x * (zm.y + zr.y) - w.y * (zm.x - zr.x)) * inv_l;
-          const double num = (xd[LdsView<1, true>::slot(N - m)] + sN) - xd[LdsView<1, true>::slot(m)] -
-                             (double)two_c;
+          const double s_nmv = LIN ? xd[s_nm - set] : xd[LdsView<1, true>::slot(N - m)];
+          const double s_mv = LIN ? xd[s_m + set] : xd[LdsView<1, true>::slot(m)];
+          const double num = (s_nmv + sN) - s_mv - (double)two_c;
           const double sum = (m >= N - kTailLags) ? (double)dtail[e] : num;
           const double dm = sum * ld_f64(ramp_r, (uint32_t)m * 8u);
           // lag 0 pairs every frame with itself: D(q, 0) = 0 exactly by definition
           drow[m] = (m == 0) ? 0.0f : (float)dm;
         }
       }
+      
     }
   }
 }
