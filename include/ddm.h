@@ -124,12 +124,25 @@ ddm_status ddm_plan_set_workspace(ddm_plan_t plan, void* workspace_dev, size_t b
  * Device-side outcomes come back without stalling the host: each call enqueues
  * a copy of them, and each later call takes in those that have completed,
  * checked without waiting (the host waits only when it is 4 calls ahead of the
- * device).  From then on, the call returns DDM_WARN_FP16_SATURATED (result
- * written) once any FP16 spectrum value has been clipped since the plan was
- * created, and returns DDM_ERR_HIP (enqueuing nothing) once for an earlier
+ * device).  The call returns DDM_WARN_FP16_SATURATED (result written) when
+ * FP16 spectrum values clipped by earlier calls have come back since the last
+ * report, and returns DDM_ERR_HIP (enqueuing nothing) once for an earlier
  * call whose single-launch step one ran out of time in a wait (that call's D
- * is not valid).  Calls made inside a HIP graph capture hand nothing back. */
+ * is not valid).  ddm_plan_status reports the outcome of every call made so
+ * far, its last call included.  Calls made inside a HIP graph capture hand
+ * nothing back to the plan (a batch collects them per stack). */
 ddm_status ddm_structure_function(ddm_plan_t plan, const void* frames_dev, float* D_dev);
+
+/* Synchronise the plan's stream and report the device-side outcomes of every
+ * call since the last report, then clear them: DDM_ERR_HIP if a single-launch
+ * step one ran out of time in a wait (that call's D is not valid; the message
+ * says so), else DDM_WARN_FP16_SATURATED if FP16 spectrum values were clipped,
+ * else DDM_OK.  DDM_ERR_STATE inside a graph capture.  Setting DDM_STEP1_FAIL=1
+ * in the environment before a plan is created makes that plan's single-launch
+ * step one start with its error flag raised: every wait gives up at once and
+ * the kernel exits normally with an invalid result, which this call reports
+ * (for testing the reporting path). */
+ddm_status ddm_plan_status(ddm_plan_t plan);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
@@ -193,9 +206,32 @@ ddm_status ddm_batch_set_workspace(ddm_batch_t batch, void* workspace_dev, size_
 /* ddm_plan_autotune for every stack (needs the workspace). */
 ddm_status ddm_batch_autotune(ddm_batch_t batch);
 /* frames_dev[i] [N_i][H_i][W_i] -> D_dev[i] [n_q_i][M_i]; both arrays are host
- * arrays of n_stacks device pointers. */
+ * arrays of n_stacks device pointers.  Each stack's step-one outcome is
+ * copied back after the graph through a ring of pinned slots (the host waits
+ * only when it is 4 calls ahead); the call returns DDM_ERR_HIP (enqueuing
+ * nothing) once when an earlier call's outcomes that have come back name a
+ * stack whose step one ran out of time in a wait. */
 ddm_status ddm_batch_structure_function(ddm_batch_t batch, const void* const* frames_dev,
                                         float* const* D_dev);
+/* Azimuthal |q| bins of one stack computed inside the batch (as
+ * ddm_radial_average: T[b] <= k2 < T[b+1], weights 2 for 0 < kx < W/2, FP64
+ * fixed-order sums; bit-identical to ddm_radial_average on the stack's D).
+ * thresholds_host [n_bins + 1] is copied before the call returns; n_bins = 0
+ * removes the stack's bins.  Synchronises the batch's streams; the next call
+ * captures a new graph. */
+ddm_status ddm_batch_set_bins(ddm_batch_t batch, int32_t stack, const int64_t* thresholds_host, int32_t n_bins);
+/* ddm_batch_structure_function plus the bins of every stack that has them:
+ * Dbar_dev[i] [n_bins_i][M_i] float64 and counts_dev[i] [n_bins_i] int64
+ * (host arrays of n_stacks device pointers; entries of stacks without bins are
+ * ignored and may be NULL).  Each stack's radial kernel runs on its lane right
+ * after its D, inside the same graph. */
+ddm_status ddm_batch_structure_function_binned(ddm_batch_t batch, const void* const* frames_dev, float* const* D_dev,
+                                               double* const* Dbar_dev, int64_t* const* counts_dev);
+/* Synchronise and report every call since the last report: DDM_ERR_HIP if any
+ * stack's step one ran out of time in a wait (its D not valid), else DDM_OK;
+ * stack_status_host [n_stacks] (may be NULL) receives each stack's status.
+ * Clears what it reports. */
+ddm_status ddm_batch_status(ddm_batch_t batch, int32_t* stack_status_host);
 
 /* Azimuthal average of D over |q| bins (standard DDM reduction; not in the
  * paper).  Bin b holds the kept q with T[b] <= k2 < T[b+1], T =

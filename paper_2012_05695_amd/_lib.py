@@ -103,6 +103,7 @@ SIGNATURES = [
     ("ddm_radial_average", c_int32,
      [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     ("ddm_plan_fp16_saturations", c_int32, [c_void_p, P(c_int64)]),
+    ("ddm_plan_status", c_int32, [c_void_p]),
     ("ddm_plan_set_profiling", c_int32, [c_void_p, c_uint32]),
     ("ddm_plan_get_profile", c_int32, [c_void_p, c_uint32, P(ctypes.c_double), P(c_int64)]),
     ("ddm_sample_curves", c_int32,
@@ -152,4 +153,7 @@ SIGNATURES += [
     ("ddm_batch_set_workspace", c_int32, [c_void_p, c_void_p, c_size_t]),
     ("ddm_batch_autotune", c_int32, [c_void_p]),
     ("ddm_batch_structure_function", c_int32, [c_void_p, c_void_p, c_void_p]),
+    ("ddm_batch_status", c_int32, [c_void_p, c_void_p]),
+    ("ddm_batch_set_bins", c_int32, [c_void_p, c_int32, c_void_p, c_int32]),
+    ("ddm_batch_structure_function_binned", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
 ]

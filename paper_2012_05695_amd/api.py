@@ -205,6 +205,13 @@ class Plan:
                 self._h, ctypes.c_void_p(frames.data_ptr()), ctypes.c_void_p(out.data_ptr())))
         return out
 
+    def status(self):
+        """Synchronise and report the outcomes of every call since the last
+        report (ddm_plan_status): raises DdmError on a failed step one; returns
+        DDM_OK or DDM_WARN_FP16_SATURATED."""
+        with torch.cuda.device(self.device):
+            return _check(_lib.ddm_plan_status(self._h))
+
     def fp16_saturations(self):
         """Spectrum components clipped by the FP16 store since plan creation (syncs)."""
         c = ctypes.c_int64()
@@ -482,7 +489,30 @@ class Batch:
         with torch.cuda.device(self.device):
             _check(_lib.ddm_batch_autotune(self._h))
 
-    def structure_function(self, frames, outs=None):
+    def set_bins(self, stack, thresholds):
+        """|q| bins of one stack, computed inside the batch (ddm_batch_set_bins);
+        an empty or one-entry threshold list removes them."""
+        thr = np.ascontiguousarray(np.asarray(thresholds, dtype=np.int64))
+        nb = max(len(thr) - 1, 0)
+        if len(thr) == 0:
+            thr = np.zeros(1, dtype=np.int64)
+        with torch.cuda.device(self.device):
+            _check(_lib.ddm_batch_set_bins(self._h, int(stack), ctypes.c_void_p(thr.ctypes.data), nb))
+        self.n_bins = getattr(self, "n_bins", [0] * len(self._descs))
+        self.n_bins[int(stack)] = nb
+
+    def structure_function_binned(self, frames, outs=None):
+        """frames -> (D list, Dbar list, counts list); stacks without bins give None."""
+        n = len(self._descs)
+        nbins = getattr(self, "n_bins", [0] * n)
+        dbar = [torch.empty((nbins[i], self.max_lag[i]), dtype=torch.float64, device=frames[i].device)
+                if nbins[i] else None for i in range(n)]
+        cnt = [torch.empty((nbins[i],), dtype=torch.int64, device=frames[i].device) if nbins[i] else None
+               for i in range(n)]
+        outs = self.structure_function(frames, outs, _bins=(dbar, cnt))
+        return outs, dbar, cnt
+
+    def structure_function(self, frames, outs=None, _bins=None):
         """frames: list of [N, H, W] device tensors -> list of D [n_q, M] float32."""
         n = len(self._descs)
         assert len(frames) == n
@@ -498,5 +528,22 @@ class Batch:
         fp = (ctypes.c_void_p * n)(*[f.data_ptr() for f in frames])
         dp = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
         with torch.cuda.device(self.device):
-            _check(_lib.ddm_batch_structure_function(self._h, fp, dp))
+            if _bins is None:
+                _check(_lib.ddm_batch_structure_function(self._h, fp, dp))
+            else:
+                bp = (ctypes.c_void_p * n)(*[t.data_ptr() if t is not None else 0 for t in _bins[0]])
+                cp = (ctypes.c_void_p * n)(*[t.data_ptr() if t is not None else 0 for t in _bins[1]])
+                _check(_lib.ddm_batch_structure_function_binned(self._h, fp, dp, bp, cp))
         return outs
+
+    def status(self):
+        """Per-stack statuses of every call since the last report
+        (ddm_batch_status, synchronises): a list of DDM_OK / DDM_ERR_HIP codes;
+        does not raise."""
+        n = len(self._descs)
+        out = (ctypes.c_int32 * n)()
+        with torch.cuda.device(self.device):
+            st = _lib.ddm_batch_status(self._h, out)
+        if st not in (L.DDM_OK, L.DDM_ERR_HIP):
+            _check(st)
+        return [int(x) for x in out]

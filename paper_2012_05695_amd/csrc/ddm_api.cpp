@@ -117,6 +117,10 @@ struct ddm_plan_s {
   bool rb_pending[kReadback];
   int rb_next;
   bool s1_failed;  // a folded slot carried a step-one error not yet reported
+  int64_t sat_unreported;  // saturation counts folded in since the last report
+  bool s1_force_err;  // DDM_STEP1_FAIL: the single-launch step one starts with its error flag raised
+  int32_t* outcome_dev;  // when set (a batch's stack): each call leaves its step-one error flag here
+  int32_t batch_nbins;   // a batch's stack: bins set by ddm_batch_set_bins (thresholds in thr_d), else 0
   // profiling: event pairs around launches of the kinds in prof_mask
   uint32_t prof_mask;
   struct Rec { uint32_t kind; hipEvent_t a, b; };
@@ -388,6 +392,13 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
   p->rb_host = nullptr;
   p->rb_next = 0;
   p->s1_failed = false;
+  p->sat_unreported = 0;
+  p->outcome_dev = nullptr;
+  p->batch_nbins = 0;
+  {
+    const char* v = std::getenv("DDM_STEP1_FAIL");
+    p->s1_force_err = v != nullptr && std::strcmp(v, "1") == 0;
+  }
   for (int i = 0; i < kReadback; ++i) {
     p->rb_ev[i] = nullptr;
     p->rb_pending[i] = false;
@@ -537,7 +548,7 @@ static ddm_status run_step_one(ddm_plan_s* p, const void* frames, float2* inter,
       ProfScope ps(p, DDM_KERNEL_STEP1);
       e = launch_step1(p->stream, p->d.pixel, frames, p->W, p->N, p->d.precondition, inter, p->kxw, p->ncol_tiles,
                        p->kxnyq, qt, sm, s_lo, s_hi, out, p->twW, p->twH, step_one_ctl(p, inter),
-                       p->s1_maxslots, p->s1_nwg, step1_bufs(), first);
+                       p->s1_maxslots, p->s1_nwg, step1_bufs(), first ? (p->s1_force_err ? 1 : 0) : -1);
     }
     if (e != hipSuccess) return hip_fail(e, "step one launch");
     return DDM_OK;
@@ -588,6 +599,7 @@ static void rb_fold(ddm_plan_s* p, int i) {
   const int32_t* v = p->rb_host + 2 * i;
   if (v[0] != 0) p->s1_failed = true;
   p->sat_total += v[1];
+  p->sat_unreported += v[1];
   p->rb_pending[i] = false;
 }
 
@@ -673,15 +685,21 @@ static ddm_status structure_function_run(ddm_plan_s* p, const void* frames, floa
     }
     if (e != hipSuccess) return hip_fail(e, "time transform launch");
   }
-  if (readback) {
-    const int32_t* err = step_one_fused(p, fb, kSpecQB) ? step_one_ctl(p, inter) + step1_ctl_words(p->s1_maxslots) - 1
-                                                        : nullptr;
-    if (err != nullptr || sat != nullptr) {
-      e = rb_push(p, err, sat);
-      if (e != hipSuccess) return hip_fail(e, "readback copy");
-    }
+  const int32_t* err = step_one_fused(p, fb, kSpecQB) ? step_one_ctl(p, inter) + step1_ctl_words(p->s1_maxslots) - 1
+                                                      : nullptr;
+  if (p->outcome_dev != nullptr) {
+    e = err != nullptr ? launch_copy_i32(p->stream, err, p->outcome_dev, 1) : launch_fill_i32(p->stream, p->outcome_dev, 1, 0);
+    if (e != hipSuccess) return hip_fail(e, "outcome copy");
   }
-  return p->sat_total > 0 ? DDM_WARN_FP16_SATURATED : DDM_OK;
+  if (readback && (err != nullptr || sat != nullptr)) {
+    e = rb_push(p, err, sat);
+    if (e != hipSuccess) return hip_fail(e, "readback copy");
+  }
+  if (p->sat_unreported > 0) {
+    p->sat_unreported = 0;
+    return DDM_WARN_FP16_SATURATED;
+  }
+  return DDM_OK;
 }
 
 static ddm_status check_sf_args(ddm_plan_t p, const void* frames, float* D) {
@@ -753,6 +771,25 @@ ddm_status ddm_structure_function_noalloc(ddm_plan_t p, const void* frames, floa
   return st;
 }
 
+ddm_status ddm_plan_status(ddm_plan_t p) {
+  ddm_status st = check_plan(p);
+  if (st != DDM_OK) return st;
+  if (capturing(p)) return fail(DDM_ERR_STATE, "ddm_plan_status waits for the stream; not allowed during a graph capture");
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (e == hipSuccess && p->rb_host != nullptr) e = rb_collect(p, true);
+  if (e != hipSuccess) return hip_fail(e, "plan status");
+  if (p->s1_failed) {
+    p->s1_failed = false;
+    p->sat_unreported = 0;
+    return fail(DDM_ERR_HIP, "step one: a wait between its row and column work ran out; that call's result is not valid");
+  }
+  if (p->sat_unreported > 0) {
+    p->sat_unreported = 0;
+    return DDM_WARN_FP16_SATURATED;
+  }
+  return DDM_OK;
+}
+
 ddm_status ddm_plan_fp16_saturations(ddm_plan_t p, int64_t* count) {
   ddm_status st = check_plan(p);
   if (st != DDM_OK) return st;
@@ -791,18 +828,20 @@ ddm_status ddm_structure_from_spectra(ddm_plan_t p, const float* spectra, float*
   return DDM_OK;
 }
 
-ddm_status ddm_radial_average(ddm_plan_t p, const float* D, const int64_t* thr, int32_t n_bins,
-                              double* Dbar, int64_t* counts, int32_t* bin_of_q) {
-  ddm_status st = check_plan(p);
-  if (st != DDM_OK) return st;
+static ddm_status check_thresholds(const int64_t* thr, int32_t n_bins) {
   if (n_bins < 0) return fail(DDM_ERR_INVALID_ARGUMENT, "n_bins must be >= 0");
-  if (D == nullptr || thr == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "D/thresholds is NULL");
-  if (n_bins > 0 && (Dbar == nullptr || counts == nullptr))
-    return fail(DDM_ERR_INVALID_ARGUMENT, "Dbar/counts is NULL");
+  if (thr == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "thresholds is NULL");
   if (thr[0] < 0) return fail(DDM_ERR_INVALID_ARGUMENT, "thresholds must be >= 0");
   for (int b = 0; b < n_bins; ++b)
     if (thr[b + 1] < thr[b])
       return fail(DDM_ERR_INVALID_ARGUMENT, "thresholds must be non-decreasing (at %d)", b);
+  return DDM_OK;
+}
+
+// The plan's device copy of the bin thresholds (checked), sent on its stream
+// through the pinned buffer once the previous launch that read the device copy
+// has finished; unchanged thresholds are not sent again.
+static ddm_status upload_thresholds(ddm_plan_s* p, const int64_t* thr, int32_t n_bins) {
   const size_t nthr = (size_t)n_bins + 1;
   const size_t need = nthr * sizeof(int64_t);
   hipError_t e = hipSuccess;
@@ -810,8 +849,6 @@ ddm_status ddm_radial_average(ddm_plan_t p, const float* D, const int64_t* thr, 
     p->thr_ev = nullptr;
     return hip_fail(e, "hipEventCreate(thresholds)");
   }
-  // new thresholds go through the pinned buffer once the previous launch that
-  // read the device copy has finished; unchanged ones are not sent again
   if (p->thr_last.size() != nthr || std::memcmp(p->thr_last.data(), thr, need) != 0) {
     p->thr_last.clear();
     if ((e = hipEventSynchronize(p->thr_ev)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
@@ -834,6 +871,19 @@ ddm_status ddm_radial_average(ddm_plan_t p, const float* D, const int64_t* thr, 
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(thresholds)");
     p->thr_last.assign(thr, thr + nthr);
   }
+  return DDM_OK;
+}
+
+ddm_status ddm_radial_average(ddm_plan_t p, const float* D, const int64_t* thr, int32_t n_bins,
+                              double* Dbar, int64_t* counts, int32_t* bin_of_q) {
+  ddm_status st = check_plan(p);
+  if (st != DDM_OK) return st;
+  if (D == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "D is NULL");
+  if ((st = check_thresholds(thr, n_bins)) != DDM_OK) return st;
+  if (n_bins > 0 && (Dbar == nullptr || counts == nullptr))
+    return fail(DDM_ERR_INVALID_ARGUMENT, "Dbar/counts is NULL");
+  if ((st = upload_thresholds(p, thr, n_bins)) != DDM_OK) return st;
+  hipError_t e;
   QTable qt{p->qoff_d, p->kxcnt_d};
   ProfScope ps(p, DDM_KERNEL_RADIAL);
   e = launch_radial(p->stream, D, p->nq, p->M, p->W, p->H, p->ca, p->cc, qt, p->thr_d, n_bins, Dbar,
@@ -1048,8 +1098,19 @@ struct ddm_batch_s {
   hipGraphExec_t exec;
   std::vector<const void*> g_frames;
   std::vector<float*> g_D;
+  std::vector<double*> g_Dbar;
+  std::vector<int64_t*> g_counts;
   void* ws;
   size_t ws_bytes;
+  // per-stack step-one error flags: written by the graph into flags_d, copied
+  // after each launch into a ring of pinned slots (like a plan's readback), and
+  // folded into `failed` once a slot's event has completed
+  int32_t* flags_d;
+  int32_t* flags_h;  // pinned [kReadback][n]
+  hipEvent_t fl_ev[kReadback];
+  bool fl_pending[kReadback];
+  int fl_next;
+  std::vector<int32_t> failed;
 };
 static constexpr uint32_t kBatchMagic = 0x44444d42u;
 
@@ -1061,6 +1122,10 @@ static ddm_status check_batch(ddm_batch_t b) {
 
 static void batch_free(ddm_batch_s* b) {
   if (b->exec) hipGraphExecDestroy(b->exec);
+  for (int i = 0; i < kReadback; ++i)
+    if (b->fl_ev[i]) hipEventDestroy(b->fl_ev[i]);
+  if (b->flags_h) hipHostFree(b->flags_h);
+  if (b->flags_d) hipFree(b->flags_d);
   if (b->root) hipStreamDestroy(b->root);
   if (b->in_ev) hipEventDestroy(b->in_ev);
   if (b->out_ev) hipEventDestroy(b->out_ev);
@@ -1090,10 +1155,23 @@ ddm_status ddm_batch_create(const ddm_plan_desc* descs, int32_t n, int32_t lanes
   b->ws_bytes = 0;
   b->root = nullptr;
   b->in_ev = b->out_ev = nullptr;
+  b->flags_d = nullptr;
+  b->flags_h = nullptr;
+  b->fl_next = 0;
+  for (int i = 0; i < kReadback; ++i) {
+    b->fl_ev[i] = nullptr;
+    b->fl_pending[i] = false;
+  }
+  b->failed.assign(n, 0);
   {
     hipError_t e0 = hipStreamCreateWithFlags(&b->root, hipStreamNonBlocking);
     if (e0 == hipSuccess) e0 = hipEventCreateWithFlags(&b->in_ev, hipEventDisableTiming);
     if (e0 == hipSuccess) e0 = hipEventCreateWithFlags(&b->out_ev, hipEventDisableTiming);
+    if (e0 == hipSuccess) e0 = hipMalloc((void**)&b->flags_d, (size_t)n * sizeof(int32_t));
+    if (e0 == hipSuccess)
+      e0 = hipHostMalloc((void**)&b->flags_h, (size_t)kReadback * n * sizeof(int32_t), hipHostMallocDefault);
+    for (int i = 0; i < kReadback && e0 == hipSuccess; ++i)
+      e0 = hipEventCreateWithFlags(&b->fl_ev[i], hipEventDisableTiming);
     if (e0 != hipSuccess) {
       batch_free(b);
       return hip_fail(e0, "batch stream setup");
@@ -1133,6 +1211,7 @@ ddm_status ddm_batch_create(const ddm_plan_desc* descs, int32_t n, int32_t lanes
       return fail(st, "stack %d: %s", i, msg.c_str());
     }
     b->plans.push_back(p);
+    p->outcome_dev = b->flags_d + i;
     size_t mn;
     ddm_plan_workspace_size(p, &mn, &full[i]);
     work[i] = (double)d.n_frames * d.width * d.height;
@@ -1226,13 +1305,59 @@ ddm_status ddm_batch_autotune(ddm_batch_t b) {
   return DDM_OK;
 }
 
-static ddm_status batch_enqueue(ddm_batch_s* b, const void* const* frames, float* const* D) {
+// Fold flag slot i (its copy has completed) into the per-stack failures.
+static void batch_fold(ddm_batch_s* b, int i) {
+  const size_t n = b->plans.size();
+  const int32_t* v = b->flags_h + (size_t)i * n;
+  for (size_t k = 0; k < n; ++k)
+    if (v[k] != 0) b->failed[k] = 1;
+  b->fl_pending[i] = false;
+}
+
+// Fold every completed slot, oldest first; wait for all of them when `wait`.
+static hipError_t batch_collect(ddm_batch_s* b, bool wait) {
+  for (int k = 0; k < kReadback; ++k) {
+    const int i = (b->fl_next + k) % kReadback;
+    if (!b->fl_pending[i]) continue;
+    hipError_t e = wait ? hipEventSynchronize(b->fl_ev[i]) : hipEventQuery(b->fl_ev[i]);
+    if (e == hipErrorNotReady) return hipSuccess;
+    if (e != hipSuccess) return e;
+    batch_fold(b, i);
+  }
+  return hipSuccess;
+}
+
+// Report (and clear) the failed stacks folded so far.
+static ddm_status batch_report(ddm_batch_s* b, int32_t* stack_status) {
+  const size_t n = b->plans.size();
+  std::string bad;
+  for (size_t k = 0; k < n; ++k) {
+    if (stack_status) stack_status[k] = b->failed[k] ? DDM_ERR_HIP : DDM_OK;
+    if (b->failed[k] && bad.size() < 200) bad += (bad.empty() ? "" : ", ") + std::to_string(k);
+    b->failed[k] = 0;
+  }
+  if (!bad.empty())
+    return fail(DDM_ERR_HIP, "stack(s) %s: step one's wait between its row and column work ran out; "
+                             "their D is not valid", bad.c_str());
+  return DDM_OK;
+}
+
+static ddm_status batch_enqueue(ddm_batch_s* b, const void* const* frames, float* const* D, double* const* Dbar,
+                                int64_t* const* counts) {
   hipError_t e = hipEventRecord(b->fork, b->root);
   for (size_t l = 0; l < b->lanes.size() && e == hipSuccess; ++l) e = hipStreamWaitEvent(b->lanes[l], b->fork, 0);
   if (e != hipSuccess) return hip_fail(e, "batch fork");
   for (size_t i = 0; i < b->plans.size(); ++i) {
-    ddm_status st = ddm_structure_function(b->plans[i], frames[i], D[i]);
+    ddm_plan_s* p = b->plans[i];
+    ddm_status st = ddm_structure_function(p, frames[i], D[i]);
     if (st != DDM_OK) return st;
+    if (Dbar != nullptr && p->batch_nbins > 0) {
+      // the stack's |q| bins right after its D, on its lane
+      QTable qt{p->qoff_d, p->kxcnt_d};
+      e = launch_radial(p->stream, D[i], p->nq, p->M, p->W, p->H, p->ca, p->cc, qt, p->thr_d, p->batch_nbins,
+                        Dbar[i], counts[i], nullptr);
+      if (e != hipSuccess) return hip_fail(e, "batch radial average launch");
+    }
   }
   for (size_t l = 0; l < b->lanes.size() && e == hipSuccess; ++l) {
     e = hipEventRecord(b->join[l], b->lanes[l]);
@@ -1242,18 +1367,67 @@ static ddm_status batch_enqueue(ddm_batch_s* b, const void* const* frames, float
   return DDM_OK;
 }
 
+ddm_status ddm_batch_set_bins(ddm_batch_t b, int32_t stack, const int64_t* thr, int32_t n_bins) {
+  ddm_status st = check_batch(b);
+  if (st != DDM_OK) return st;
+  if (stack < 0 || stack >= (int)b->plans.size()) return fail(DDM_ERR_INVALID_ARGUMENT, "stack out of range");
+  if ((st = check_thresholds(thr, n_bins)) != DDM_OK) return st;
+  ddm_plan_s* p = b->plans[stack];
+  // the plan's stream is a lane: wait for work in flight before replacing the thresholds
+  hipError_t e = hipStreamSynchronize(b->root);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return hip_fail(e, "batch bins");
+  if ((st = upload_thresholds(p, thr, n_bins)) != DDM_OK) return st;
+  if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return hip_fail(e, "batch bins");
+  p->batch_nbins = n_bins;
+  if (b->exec) {  // the captured graph holds the old bins
+    hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  return DDM_OK;
+}
+
+static ddm_status batch_run(ddm_batch_t b, const void* const* frames, float* const* D, double* const* Dbar,
+                            int64_t* const* counts);
+
 ddm_status ddm_batch_structure_function(ddm_batch_t b, const void* const* frames, float* const* D) {
+  return batch_run(b, frames, D, nullptr, nullptr);
+}
+
+ddm_status ddm_batch_structure_function_binned(ddm_batch_t b, const void* const* frames, float* const* D,
+                                               double* const* Dbar, int64_t* const* counts) {
+  ddm_status st = check_batch(b);
+  if (st != DDM_OK) return st;
+  if (Dbar == nullptr || counts == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "Dbar/counts arrays are NULL");
+  for (size_t i = 0; i < b->plans.size(); ++i)
+    if (b->plans[i]->batch_nbins > 0 && (Dbar[i] == nullptr || counts[i] == nullptr))
+      return fail(DDM_ERR_INVALID_ARGUMENT, "stack %zu has bins but a NULL Dbar/counts pointer", i);
+  return batch_run(b, frames, D, Dbar, counts);
+}
+
+static ddm_status batch_run(ddm_batch_t b, const void* const* frames, float* const* D, double* const* Dbar,
+                            int64_t* const* counts) {
   ddm_status st = check_batch(b);
   if (st != DDM_OK) return st;
   if (frames == nullptr || D == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "pointer arrays are NULL");
   if (b->ws == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "no workspace attached");
   const size_t n = b->plans.size();
+  {
+    // outcomes of earlier calls that have come back (checked without waiting)
+    hipError_t e0 = batch_collect(b, false);
+    if (e0 != hipSuccess) return hip_fail(e0, "batch readback");
+    st = batch_report(b, nullptr);
+    if (st != DDM_OK) return st;
+  }
   for (size_t i = 0; i < n; ++i) {
     if (frames[i] == nullptr || D[i] == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "stack %zu: NULL pointer", i);
     if (((uintptr_t)frames[i] & 15) != 0) return fail(DDM_ERR_INVALID_ARGUMENT, "stack %zu: frames not 16-byte aligned", i);
   }
   bool same = b->exec != nullptr && b->g_frames.size() == n;
-  for (size_t i = 0; same && i < n; ++i) same = b->g_frames[i] == frames[i] && b->g_D[i] == D[i];
+  for (size_t i = 0; same && i < n; ++i) {
+    same = b->g_frames[i] == frames[i] && b->g_D[i] == D[i] &&
+           b->g_Dbar[i] == (Dbar ? Dbar[i] : nullptr) && b->g_counts[i] == (counts ? counts[i] : nullptr);
+  }
   if (!same) {
     if (b->exec) {
       hipGraphExecDestroy(b->exec);
@@ -1261,7 +1435,7 @@ ddm_status ddm_batch_structure_function(ddm_batch_t b, const void* const* frames
     }
     hipError_t e = hipStreamBeginCapture(b->root, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    st = batch_enqueue(b, frames, D);
+    st = batch_enqueue(b, frames, D, Dbar, counts);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->root, &g);
     if (st != DDM_OK) {
@@ -1277,6 +1451,12 @@ ddm_status ddm_batch_structure_function(ddm_batch_t b, const void* const* frames
     }
     b->g_frames.assign(frames, frames + n);
     b->g_D.assign(D, D + n);
+    b->g_Dbar.assign(n, nullptr);
+    b->g_counts.assign(n, nullptr);
+    for (size_t i = 0; i < n; ++i) {
+      if (Dbar) b->g_Dbar[i] = Dbar[i];
+      if (counts) b->g_counts[i] = counts[i];
+    }
   }
   // order after the caller's stream, launch, and order the caller's stream after it
   hipError_t e = hipEventRecord(b->in_ev, b->stream);
@@ -1285,7 +1465,28 @@ ddm_status ddm_batch_structure_function(ddm_batch_t b, const void* const* frames
   if (e == hipSuccess) e = hipEventRecord(b->out_ev, b->root);
   if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->out_ev, 0);
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  // the per-stack flags go back through the next ring slot (waiting only when
+  // that slot is still in flight, kReadback calls back)
+  const int i = b->fl_next;
+  if (b->fl_pending[i]) {
+    if ((e = hipEventSynchronize(b->fl_ev[i])) != hipSuccess) return hip_fail(e, "batch readback");
+    batch_fold(b, i);
+  }
+  e = hipMemcpyAsync(b->flags_h + (size_t)i * n, b->flags_d, n * sizeof(int32_t), hipMemcpyDeviceToHost, b->root);
+  if (e == hipSuccess) e = hipEventRecord(b->fl_ev[i], b->root);
+  if (e != hipSuccess) return hip_fail(e, "batch readback copy");
+  b->fl_pending[i] = true;
+  b->fl_next = (i + 1) % kReadback;
   return DDM_OK;
+}
+
+ddm_status ddm_batch_status(ddm_batch_t b, int32_t* stack_status_host) {
+  ddm_status st = check_batch(b);
+  if (st != DDM_OK) return st;
+  hipError_t e = hipStreamSynchronize(b->root);
+  if (e == hipSuccess) e = batch_collect(b, true);
+  if (e != hipSuccess) return hip_fail(e, "batch status");
+  return batch_report(b, stack_status_host);
 }
 
 }  // extern "C"

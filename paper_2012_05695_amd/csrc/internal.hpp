@@ -103,8 +103,10 @@ hipError_t launch_col(hipStream_t s, const float2* inter, int H, int kxw, int nt
 // frames W = H in {64, 128, 256, 512} with full column tiles.  ctl:
 // step1_ctl_words(maxslots) ints of device memory (initialised by the launch);
 // maxslots >= N + nwg / (items per frame) + 4; the last word is an error flag
-// (non-zero if a wait ran out), cleared by the launch when clear_err, else
-// kept from the previous launch (a later launch then does no work).
+// (non-zero if a wait ran out), set by the launch to err_init when err_init >= 0
+// (0 clears it; 1 makes every wait give up at once, so the kernel exits with its
+// result invalid), else kept from the previous launch (a later launch then does
+// no work).
 bool step1_fusable(int W, int H, int ncol_tiles, int kxw);
 int step1_bufs();
 int step1_workgroups(int W);
@@ -112,10 +114,11 @@ __host__ __device__ size_t step1_ctl_words(int maxslots);
 hipError_t launch_step1(hipStream_t s, int pixel, const void* frames, int W, int N, int precondition,
                         float2* bufs, int kxw, int ntiles, int kxnyq, QTable qt, SlotMap sm, int64_t s_lo,
                         int64_t s_hi, SpecOut out, const float2* twW, const float2* twH, int* ctl, int maxslots,
-                        int nwg, int nbufs, bool clear_err);
+                        int nwg, int nbufs, int err_init);
 
 hipError_t launch_qexp(hipStream_t s, const float2* pilot, int np, int64_t nq, int32_t* qexp);
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
+hipError_t launch_copy_i32(hipStream_t s, const int32_t* src, int32_t* dst, int n);
 
 // spec: the group's slots, complex FP32, or complex FP16 scaled by 2^qexp[q]
 // when qexp is non-null (qexp indexed by wave vector q).  qmap: wave vector of

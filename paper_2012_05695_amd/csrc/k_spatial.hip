@@ -606,15 +606,24 @@ bool step1_fusable(int W, int H, int ncol_tiles, int kxw) {
 }
 
 // control words: per XCD [ticket, fidx[maxslots] = kUnset, rows[maxslots], cols[maxslots]], then
-// the global frame counter and the error flag, all 0 except fidx (the error
-// flag is left as it is unless clear_err)
-__global__ void k_step1_init(int* ctl, int maxslots, int clear_err) {
-  const int64_t total = (int64_t)step1_ctl_words(maxslots) - (clear_err ? 0 : 1);
+// the global frame counter and the error flag, all 0 except fidx; the error
+// flag is set to err_init when err_init >= 0, else left as it is
+__global__ void k_step1_init(int* ctl, int maxslots, int err_init) {
+  const int64_t words = (int64_t)step1_ctl_words(maxslots);
   const int64_t per = 1 + 3 * (int64_t)maxslots;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t o = i % per;
-    ctl[i] = (i < 8 * per && o >= 1 && o <= maxslots) ? kUnset : 0;
+    if (i == words - 1) {
+      if (err_init >= 0) ctl[i] = err_init;
+    } else {
+      ctl[i] = (i < 8 * per && o >= 1 && o <= maxslots) ? kUnset : 0;
+    }
   }
+}
+
+__global__ void k_copy_i32(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
 }
 
 template <int W, typename PIX>
@@ -643,9 +652,9 @@ int step1_workgroups(int W) {
 hipError_t launch_step1(hipStream_t s, int pixel, const void* frames, int W, int N, int precondition,
                         float2* bufs, int kxw, int ntiles, int kxnyq, QTable qt, SlotMap sm, int64_t s_lo,
                         int64_t s_hi, SpecOut out, const float2* twW, const float2* twH, int* ctl, int maxslots,
-                        int nwg, int nbufs, bool clear_err) {
+                        int nwg, int nbufs, int err_init) {
   if (nbufs < 2) return hipErrorInvalidValue;  // a row item would wait on a later ticket
-  hipLaunchKernelGGL(k_step1_init, dim3(64), dim3(256), 0, s, ctl, maxslots, clear_err ? 1 : 0);
+  hipLaunchKernelGGL(k_step1_init, dim3(64), dim3(256), 0, s, ctl, maxslots, err_init);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int pack = kxnyq > 0, lo = (int)s_lo, hi = (int)s_hi;
@@ -667,6 +676,12 @@ hipError_t launch_step1(hipStream_t s, int pixel, const void* frames, int W, int
 hipError_t launch_qexp(hipStream_t s, const float2* pilot, int np, int64_t nq, int32_t* qexp) {
   if (nq == 0) return hipSuccess;
   hipLaunchKernelGGL(k_qexp, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, pilot, np, nq, qexp);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_i32(hipStream_t s, const int32_t* src, int32_t* dst, int n) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
   return hipGetLastError();
 }
 

@@ -70,3 +70,34 @@ def test_autotune_keeps_parity(gpu):
     rows = np.flatnonzero(np.isin(kx, [0, 3, 64]))
     e = per_q_error(D.cpu().numpy()[rows], Do)
     assert e.max() <= TOL_F32
+
+
+def test_batch_bins_match_radial_average(gpu):
+    """|q| bins inside the batch graph equal ddm_radial_average on the batch's
+    D bit for bit; counts equal the full-plane lattice counts of the oracle."""
+    print("case: batch with bins on stacks 0, 2 and 4", flush=True)
+    from oracle import dft, radial
+    fr = stacks()
+    batch = gpu.Batch(SHAPES, lanes=3)
+    thr = {0: gpu.integer_bin_thresholds(40), 2: gpu.integer_bin_thresholds(60),
+           4: np.array([0, 3, 50, 400, 3000, 40000], dtype=np.int64)}
+    for i, t in thr.items():
+        batch.set_bins(i, t)
+    D, Dbar, cnt = batch.structure_function_binned(fr)
+    D2, Dbar2, cnt2 = batch.structure_function_binned(fr)      # a second capture (new outputs)
+    torch.cuda.synchronize()
+    for i, (W, H, N) in enumerate(SHAPES):
+        if i not in thr:
+            assert Dbar[i] is None
+            continue
+        plan = gpu.Plan(W, H, N)
+        ref, rc, _ = plan.radial_average(D[i], thr[i], bin_of_q=False)
+        torch.cuda.synchronize()
+        assert torch.equal(Dbar[i], ref) and torch.equal(cnt[i], rc), i
+        assert torch.equal(Dbar2[i], ref) and torch.equal(cnt2[i], rc), i
+        kx, ky = plan.q_index()
+        b = radial.bin_index(dft.k2_of(kx, ky, W, H), thr[i])
+        w = radial.weights(kx, W)
+        c_o = np.bincount(b[b >= 0], weights=w[b >= 0], minlength=len(thr[i]) - 1).astype(np.int64)
+        np.testing.assert_array_equal(cnt[i].cpu().numpy(), c_o)
+    assert batch.status() == [0] * len(SHAPES)
