@@ -34,13 +34,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="paper", choices=["paper", "plain", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-columns", type=int, default=0,
-                    help="kx columns of the oracle sample (0: all, i.e. the whole workload)")
+    ap.add_argument("--cpu-columns", type=int, default=None,
+                    help="kx columns of the oracle sample (0: all, i.e. the whole workload; "
+                         "default all for the 512x512 workload, 2 for 2048x2048)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the tau-fit leg (network training + LM vs MLP+LM on 1024x1024x2048)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-stacks leg (graph launch vs a loop of single plans)")
-    ap.add_argument("--batched-stacks", type=int, default=16)
+    ap.add_argument("--batched-stacks", type=int, default=64)
     ap.add_argument("--learned-curves", type=int, default=1_000_000)
     ap.add_argument("--learned-epochs", type=int, default=30)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -240,37 +241,53 @@ def batched_leg(n_stacks, log):
         (n_stacks, total, sum(f.numel() * 2 for f in frames) / 1e9))
     batch = api.Batch(shapes, lanes=4)
     batch.allocate_workspace()
-    outs = batch.structure_function(frames)
-    # the loop's plans run one after another on one stream: one shared workspace
+    # integer |q| bins (b = round |k|) of every stack, computed inside the graph
+    thr = [api.integer_bin_thresholds(int(w * 0.7072) + 2) for (w, _, _) in shapes]
+    for i, t in enumerate(thr):
+        batch.set_bins(i, t)
+    outs, dbar, cnt = batch.structure_function_binned(frames)
+    # the loop's plans run one after another on one stream, after the batch: they
+    # share the batch's workspace (it holds the largest stack's full workspace)
     plans = [api.Plan(w, h, n) for (w, h, n) in shapes]
-    shared = torch.empty(max(p.workspace_size()[1] for p in plans), dtype=torch.uint8, device="cuda")
+    shared = batch._ws
+    assert shared.numel() >= max(p.workspace_size()[1] for p in plans)
     for p in plans:
         p.set_workspace(shared)
-    for p, f, o in zip(plans, frames, outs):
-        p.structure_function(f, out=o)
+
+    def loop():
+        for p, f, o, t in zip(plans, frames, outs, thr):
+            p.structure_function(f, out=o)
+            p.radial_average(o, t, bin_of_q=False)
+
+    loop()
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     reps = 3
     ev[0].record()
     for _ in range(reps):
-        batch.structure_function(frames, outs)
+        batch.structure_function_binned(frames, outs, dbar, cnt)
     ev[1].record()
     for _ in range(reps):
-        for p, f, o in zip(plans, frames, outs):
-            p.structure_function(f, out=o)
+        loop()
     ev[2].record()
     torch.cuda.synchronize()
     t_b = ev[0].elapsed_time(ev[1]) / reps
     t_l = ev[1].elapsed_time(ev[2]) / reps
+    stack_status = batch.status()
+    if any(st != 0 for st in stack_status):
+        raise RuntimeError("batched leg: stacks reported errors: %s" % stack_status)
     for p in plans:
+        p.status()
         p.close()
     batch.close()
-    del frames, outs, shared
+    del frames, outs, shared, dbar, cnt
     torch.cuda.empty_cache()
     return {"stacks": n_stacks, "shapes": ["%dx%dx%d" % s for s in shapes], "frames": total,
             "batched_ms": t_b, "loop_ms": t_l, "batched_frames_per_s": total / (t_b * 1e-3),
             "loop_frames_per_s": total / (t_l * 1e-3),
-            "recipe": "%d stacks (of the 64 in the batched workload's recipe), seeds 5000+i" % n_stacks}
+            "work": "D of every stack and its integer |q| bins; graph launch (4 lanes) vs the same "
+                    "calls one after another on one stream",
+            "recipe": "%d stacks of the batched workload's recipe, seeds 5000+i" % n_stacks}
 
 
 def main():
@@ -344,6 +361,7 @@ def main():
     ms_step = ev0.elapsed_time(ev1) / args.steps
     k_ms, k_n = plan.profile(dominant)
     plan.set_profiling([])
+    plan.status()  # raises if any timed call's step one reported an error
 
     pix_bytes = 1 if recipe["pixel"] == "u8" else 2
     per, whole = algorithmic_bytes(W, H, N, M, nq, pix_bytes)
@@ -393,8 +411,7 @@ def main():
         "algorithmic_bytes_whole_path": whole,
         "kernel_ms_per_step": {k: v[0] for k, v in prof.items()},
         "roofline": dict(roof, **{
-            "traffic": (recorded_traffic("k_" + dominant, "%dx%dx%d" % (W, H, N))
-                        if args.config == "paper" else None),
+            "traffic": recorded_traffic("k_" + dominant, "%dx%dx%d" % (W, H, N)),
             "avg_launch_ms": avg_launch_ms, "launches": k_n,
             "algorithmic_bytes_per_launch": bytes_per_launch}),
     }
@@ -402,6 +419,17 @@ def main():
     out["kernel_rooflines"] = {k: kernel_roof(k, v[0] / v[1], v[1], W, H, N, M, nq, pix_bytes)
                                for k, v in prof.items()}
     out["copy_GBs"] = copy_bandwidth()
+    if args.config == "large":
+        args.no_batched = args.no_learned = True  # legs of the other workloads
+    frames_cpu = None
+    if not args.no_cpu_baseline:
+        frames_cpu = frames.cpu()
+    if args.config != "paper":
+        del frames, D
+        plan.close()
+        torch.cuda.empty_cache()
+        finish(args, out, frames_cpu, nq)
+        return
     # the same workload with the FP16 per-q-scaled spectra store
     plan16 = api.Plan(W, H, N, pixel=recipe["pixel"], spectrum="f16")
     plan16.allocate_workspace()
@@ -417,11 +445,15 @@ def main():
     ms16 = ev0.elapsed_time(ev1) / args.steps
     out["f16_store"] = {"ms_per_step": ms16, "frames_per_s": N / (ms16 * 1e-3),
                         "saturated_values": int(plan16.fp16_saturations())}
+    plan16.status()
     plan16.close()
-    frames_cpu = frames.cpu() if not args.no_cpu_baseline else None
     del frames, D
     plan.close()
     torch.cuda.empty_cache()
+    finish(args, out, frames_cpu, nq)
+
+
+def finish(args, out, frames_cpu, nq):
     if not args.no_batched:
         print("bench: batched leg (graph launch vs loop)", file=sys.stderr, flush=True)
         out["batched"] = batched_leg(args.batched_stacks,
@@ -432,7 +464,10 @@ def main():
         out["tau_fit"] = learned_leg(lambda m: print("bench: " + m, file=sys.stderr, flush=True))
     if frames_cpu is not None:
         print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(frames_cpu, args.cpu_columns, nq)
+        cols = args.cpu_columns
+        if cols is None:
+            cols = 2 if args.config == "large" else 0
+        out["cpu_baseline"] = cpu_baseline(frames_cpu, cols, nq)
     print(json.dumps(out), flush=True)
 
 

@@ -501,14 +501,22 @@ class Batch:
         self.n_bins = getattr(self, "n_bins", [0] * len(self._descs))
         self.n_bins[int(stack)] = nb
 
-    def structure_function_binned(self, frames, outs=None):
-        """frames -> (D list, Dbar list, counts list); stacks without bins give None."""
+    def structure_function_binned(self, frames, outs=None, dbar=None, counts=None):
+        """frames -> (D list, Dbar list, counts list); stacks without bins give None.
+        Passing the lists of an earlier call reuses them (and the captured graph)."""
         n = len(self._descs)
         nbins = getattr(self, "n_bins", [0] * n)
-        dbar = [torch.empty((nbins[i], self.max_lag[i]), dtype=torch.float64, device=frames[i].device)
-                if nbins[i] else None for i in range(n)]
-        cnt = [torch.empty((nbins[i],), dtype=torch.int64, device=frames[i].device) if nbins[i] else None
-               for i in range(n)]
+        if dbar is None:
+            dbar = [torch.empty((nbins[i], self.max_lag[i]), dtype=torch.float64, device=frames[i].device)
+                    if nbins[i] else None for i in range(n)]
+        if counts is None:
+            counts = [torch.empty((nbins[i],), dtype=torch.int64, device=frames[i].device) if nbins[i] else None
+                      for i in range(n)]
+        cnt = counts
+        for i in range(n):
+            if nbins[i]:
+                _require(dbar[i], "Dbar[%d]" % i, (torch.float64,), (nbins[i], self.max_lag[i]), self.device)
+                _require(cnt[i], "counts[%d]" % i, (torch.int64,), (nbins[i],), self.device)
         outs = self.structure_function(frames, outs, _bins=(dbar, cnt))
         return outs, dbar, cnt
 

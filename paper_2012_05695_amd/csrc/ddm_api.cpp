@@ -57,7 +57,7 @@ ddm_status api_fail(ddm_status st, const char* fmt, ...) {
 
 namespace {
 
-constexpr size_t kInterTargetBytes = 64u << 20;  // row-transform intermediate per batch
+constexpr size_t kInterTargetBytes = 128u << 20;  // row-transform intermediate per batch (half the Infinity Cache)
 constexpr int kReadback = 4;                      // calls in flight before the host waits
 
 }  // namespace
@@ -283,7 +283,12 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
   p->ncol_tiles = (ncols + p->cw - 1) / p->cw;
   p->kxw = p->ncol_tiles * p->cw;
   p->frame_inter_bytes = (size_t)H * p->kxw * sizeof(float2);
-  p->fb_target = (int)std::max<size_t>(1, std::min<size_t>(N, kInterTargetBytes / p->frame_inter_bytes));
+  size_t inter_target = kInterTargetBytes;
+  if (const char* v = std::getenv("DDM_INTER_MB")) {  // tuning: row-intermediate bytes per batch
+    const long mb = std::atol(v);
+    if (mb >= 1 && mb <= 4096) inter_target = (size_t)mb << 20;
+  }
+  p->fb_target = (int)std::max<size_t>(1, std::min<size_t>(N, inter_target / p->frame_inter_bytes));
   // Step one in one launch where it applies (DDM_STEP1=split keeps the two
   // kernels): its intermediates (step1_bufs() frames per XCD) and control words
   // take the place of the batch of intermediates.
