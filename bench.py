@@ -280,11 +280,31 @@ def batched_leg(n_stacks, log):
         p.status()
         p.close()
     batch.close()
-    del frames, outs, shared, dbar, cnt
+    del shared
+    torch.cuda.empty_cache()
+    # the same batch with minimal padding (time transforms of the smallest 2^k
+    # or 3 * 2^k >= N) instead of powers of two (the length Eq. (B4) prints)
+    b2 = api.Batch(shapes, lanes=4, padding="minimal")
+    b2.allocate_workspace()
+    for i, t in enumerate(thr):
+        b2.set_bins(i, t)
+    b2.structure_function_binned(frames, outs, dbar, cnt)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        b2.structure_function_binned(frames, outs, dbar, cnt)
+    ev[1].record()
+    torch.cuda.synchronize()
+    t_p2 = ev[0].elapsed_time(ev[1]) / reps
+    if any(st != 0 for st in b2.status()):
+        raise RuntimeError("batched leg (minimal padding): stacks reported errors")
+    b2.close()
+    del frames, outs, dbar, cnt
     torch.cuda.empty_cache()
     return {"stacks": n_stacks, "shapes": ["%dx%dx%d" % s for s in shapes], "frames": total,
             "batched_ms": t_b, "loop_ms": t_l, "batched_frames_per_s": total / (t_b * 1e-3),
             "loop_frames_per_s": total / (t_l * 1e-3),
+            "batched_minimal_padding_ms": t_p2,
             "work": "D of every stack and its integer |q| bins; graph launch (4 lanes) vs the same "
                     "calls one after another on one stream",
             "recipe": "%d stacks of the batched workload's recipe, seeds 5000+i" % n_stacks}

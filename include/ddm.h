@@ -66,20 +66,28 @@ typedef enum ddm_pixel { DDM_PIX_U8 = 1, DDM_PIX_U16 = 2 } ddm_pixel;
  * Halves the spectrum traffic; D within 5e-3 of the FP32 result's accuracy. */
 typedef enum ddm_spectrum { DDM_SPEC_F32 = 0, DDM_SPEC_F16_QSCALED = 1 } ddm_spectrum;
 
+/* Zero padding of the time sequences (Eq. (B4) and the exactness statement
+ * after it: any N2 >= 2N - 1 gives D exactly).  POW2: N2 = 2L, L the smallest
+ * power of two >= N (as Eq. (B4) prints it).  MINIMAL: L the smallest of
+ * 2^k and 3 * 2^k >= N (3 * 2^k from 192 on), up to 1.5x less transform work;
+ * the 3 * 2^k transforms take radix-4/2 passes and a radix-3 pass, more LDS
+ * round trips per point, and are faster than POW2 only where N = L. */
+typedef enum ddm_padding { DDM_PAD_POW2 = 0, DDM_PAD_MINIMAL = 1 } ddm_padding;
+
 typedef struct ddm_plan_s* ddm_plan_t;
 
 typedef struct ddm_plan_desc {
   uint32_t struct_size;  /* = sizeof(ddm_plan_desc); guards ABI drift */
   int32_t width;         /* W: even, 8..4096, a power of two or 3 * a power of two */
   int32_t height;        /* H: same rules as W */
-  int32_t n_frames;      /* N >= 2 (up to 4096: time FFT length N2 <= 8192) */
+  int32_t n_frames;      /* N >= 2 (up to 8192: time FFT length N2 <= 16384) */
   int32_t max_lag;       /* M in [1, N]: lags 0..M-1 are produced; 0 means N */
   int32_t pixel;         /* ddm_pixel of the frames */
   int32_t spectrum;      /* ddm_spectrum */
   int32_t precondition;  /* 1: transform I_t - I_0 instead of I_t (D is unchanged
                             because D depends on frame differences only; it
                             shrinks the dynamic range of the FP32 transforms) */
-  int32_t reserved0;
+  int32_t padding;       /* ddm_padding of the time transform (default POW2) */
   int64_t k2_max;        /* keep q with k2 <= k2_max (the paper's low-frequency
                             restriction, section "Conclusion"); -1 keeps all */
   void* stream;          /* hipStream_t for all work of this plan; NULL = default */

@@ -38,6 +38,8 @@ DDM_PIX_U8 = 1
 DDM_PIX_U16 = 2
 DDM_SPEC_F32 = 0
 DDM_SPEC_F16_QSCALED = 1
+DDM_PAD_POW2 = 0
+DDM_PAD_MINIMAL = 1
 
 STATUS_NAMES = {
     0: "DDM_OK",
@@ -60,7 +62,7 @@ class PlanDesc(ctypes.Structure):
         ("pixel", c_int32),
         ("spectrum", c_int32),
         ("precondition", c_int32),
-        ("reserved0", c_int32),
+        ("padding", c_int32),
         ("k2_max", c_int64),
         ("stream", c_void_p),
     ]

@@ -43,6 +43,7 @@ NOALLOC_SCRATCH_BYTES = L.DDM_NOALLOC_SCRATCH_BYTES
 _PIX = {"u8": L.DDM_PIX_U8, "u16": L.DDM_PIX_U16}
 _PIX_DTYPES = {L.DDM_PIX_U8: (torch.uint8,), L.DDM_PIX_U16: (torch.uint16, torch.int16)}
 _SPEC = {"f32": L.DDM_SPEC_F32, "f16": L.DDM_SPEC_F16_QSCALED}
+_PAD = {"pow2": L.DDM_PAD_POW2, "minimal": L.DDM_PAD_MINIMAL}
 
 
 def _stream_handle(stream):
@@ -73,7 +74,7 @@ class Plan:
     """
 
     def __init__(self, width, height, n_frames, max_lag=0, pixel="u16", spectrum="f32",
-                 precondition=True, k2_max=-1, stream=None, device=None):
+                 precondition=True, k2_max=-1, padding="pow2", stream=None, device=None):
         if device is None:
             device = torch.cuda.current_device()
         self.device = int(device)
@@ -88,6 +89,7 @@ class Plan:
         d.spectrum = _SPEC[spectrum] if isinstance(spectrum, str) else int(spectrum)
         d.precondition = 1 if precondition else 0
         d.k2_max = int(k2_max)
+        d.padding = _PAD[padding] if isinstance(padding, str) else int(padding)
         with torch.cuda.device(self.device):
             d.stream = _stream_handle(stream).value
         self._desc = d
@@ -426,9 +428,9 @@ class Batch:
     """Independent stacks of uneven sizes in one graph launch (ddm_batch_* of include/ddm.h).
 
     shapes: list of (W, H, N) or dicts with Plan keyword fields (width, height,
-    n_frames, max_lag, pixel, precondition, k2_max)."""
+    n_frames, max_lag, pixel, precondition, k2_max, padding)."""
 
-    def __init__(self, shapes, lanes=4, stream=None, device=None):
+    def __init__(self, shapes, lanes=4, padding="pow2", stream=None, device=None):
         if device is None:
             device = torch.cuda.current_device()
         self.device = int(device)
@@ -445,6 +447,8 @@ class Batch:
             d.pixel = _PIX[pix] if isinstance(pix, str) else int(pix)
             d.precondition = 1 if sh.get("precondition", True) else 0
             d.k2_max = int(sh.get("k2_max", -1))
+            pad = sh.get("padding", padding)
+            d.padding = _PAD[pad] if isinstance(pad, str) else int(pad)
             self.shapes.append(sh)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):

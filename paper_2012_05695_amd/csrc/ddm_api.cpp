@@ -230,7 +230,7 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
     return fail(DDM_ERR_UNSUPPORTED,
                 "frame %dx%d: each side must be 2^k (16..4096) or 3*2^k (48..3072)", W, H);
   if (N < 2) return fail(DDM_ERR_INVALID_ARGUMENT, "n_frames must be >= 2");
-  if (N > 4096) return fail(DDM_ERR_UNSUPPORTED, "n_frames > 4096 (time FFT length > 8192)");
+  if (N > 8192) return fail(DDM_ERR_UNSUPPORTED, "n_frames > 8192 (time FFT length > 16384)");
   if (desc->max_lag < 0 || desc->max_lag > N)
     return fail(DDM_ERR_INVALID_ARGUMENT, "max_lag must be in [0, n_frames]");
   if (desc->pixel != DDM_PIX_U8 && desc->pixel != DDM_PIX_U16)
@@ -240,6 +240,8 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
   if (desc->precondition != 0 && desc->precondition != 1)
     return fail(DDM_ERR_INVALID_ARGUMENT, "precondition must be 0 or 1");
   if (desc->k2_max < -1) return fail(DDM_ERR_INVALID_ARGUMENT, "k2_max must be >= -1");
+  if (desc->padding != DDM_PAD_POW2 && desc->padding != DDM_PAD_MINIMAL)
+    return fail(DDM_ERR_INVALID_ARGUMENT, "padding must be DDM_PAD_POW2 or DDM_PAD_MINIMAL");
 
   ddm_plan_s* p = new (std::nothrow) ddm_plan_s();
   if (p == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -252,7 +254,7 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
   int l = 1;
   while (l < N) l <<= 1;
   p->n2_paper = 2 * l;
-  p->L = std::max(16, l);
+  p->L = time_length(N, desc->padding);
   const int64_t g = std::gcd(W, H);
   p->ca = (int64_t)(H / g) * (H / g);
   p->cc = (int64_t)(W / g) * (W / g);
@@ -685,7 +687,7 @@ static ddm_status structure_function_run(ddm_plan_s* p, const void* frames, floa
     if (st != DDM_OK) return st;
     {
       ProfScope ps(p, DDM_KERNEL_TIME);
-      e = launch_time(p->stream, spec, kSpecQB, s_hi - s_lo, p->N, p->M, p->twT, p->ramp, p->qmap_d + s_lo,
+      e = launch_time(p->stream, p->L, spec, kSpecQB, s_hi - s_lo, p->N, p->M, p->twT, p->ramp, p->qmap_d + s_lo,
                       qexp, D, p->tshape);
     }
     if (e != hipSuccess) return hip_fail(e, "time transform launch");
@@ -827,7 +829,7 @@ ddm_status ddm_structure_from_spectra(ddm_plan_t p, const float* spectra, float*
   hipError_t e;
   {
     ProfScope ps(p, DDM_KERNEL_TIME);
-    e = launch_time(p->stream, spectra, 1, p->nq, p->N, p->M, p->twT, p->ramp, nullptr, nullptr, D, p->tshape);
+    e = launch_time(p->stream, p->L, spectra, 1, p->nq, p->N, p->M, p->twT, p->ramp, nullptr, nullptr, D, p->tshape);
   }
   if (e != hipSuccess) return hip_fail(e, "time transform launch");
   return DDM_OK;
@@ -1048,16 +1050,18 @@ ddm_status ddm_plan_autotune(ddm_plan_t p, int32_t* E_out, int32_t* qpw_out, dou
     hipEvent_t a = nullptr, b = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
-    for (int E : {16, 8}) {
+    for (int E : {16, 8, 12}) {
       for (int qpw : {1, 2, 4, 8, 16}) {
         if (e != hipSuccess) break;
+        // 2^k lengths take E = 16 or 8 (8 from L = 512 on); 3 * 2^k lengths E = 12
+        if ((p->L % 3 == 0) != (E == 12)) continue;
         if (p->L / E < 1 || p->L % E != 0 || (E == 8 && p->L < 512)) continue;
         if (qpw * (p->L / E) > 1024 || time_lds_bytes(p->L, qpw) > 160 * 1024) continue;
         const TimeShape sh{E, qpw};
-        e = launch_time(p->stream, spec, kSpecQB, nq_t, p->N, p->M, p->twT, p->ramp, nullptr, qexp, dout, sh);
+        e = launch_time(p->stream, p->L, spec, kSpecQB, nq_t, p->N, p->M, p->twT, p->ramp, nullptr, qexp, dout, sh);
         if (e == hipSuccess) e = hipEventRecord(a, p->stream);
         for (int r = 0; r < 2 && e == hipSuccess; ++r)
-          e = launch_time(p->stream, spec, kSpecQB, nq_t, p->N, p->M, p->twT, p->ramp, nullptr, qexp, dout, sh);
+          e = launch_time(p->stream, p->L, spec, kSpecQB, nq_t, p->N, p->M, p->twT, p->ramp, nullptr, qexp, dout, sh);
         if (e == hipSuccess) e = hipEventRecord(b, p->stream);
         if (e == hipSuccess) e = hipEventSynchronize(b);
         float ms = 0.f;

@@ -131,7 +131,14 @@ struct TimeShape {
   int qpw = 0;
 };
 
-hipError_t launch_time(hipStream_t s, const void* spec, int qb, int64_t nslots_group, int N, int M,
+// Time-transform length L for N frames: the smallest 2^k >= max(N, 16); with
+// `minimal`, 3 * 2^k >= N instead when that is smaller (and at least 192).
+// N2 = 2 L >= 2 N either way.
+int time_length(int N, int minimal);
+
+// L: the plan's transform length (time_length(N) when the plan was made; twN2
+// holds 2 L entries).
+hipError_t launch_time(hipStream_t s, int L, const void* spec, int qb, int64_t nslots_group, int N, int M,
                        const float2* twN2, const double* ramp, const int32_t* qmap,
                        const int32_t* qexp, float* D_rows,
                        TimeShape shape = TimeShape{});

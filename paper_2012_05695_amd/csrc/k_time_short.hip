@@ -1,4 +1,4 @@
-// Time kernel instantiations for the short transform lengths (N <= 128).
+// Time kernel instantiations for the short transform lengths (N <= 192).
 #include "time_kernel.hpp"
 
 namespace ddm {
@@ -6,4 +6,5 @@ DDM_TIME_INSTANTIATE(16)
 DDM_TIME_INSTANTIATE(32)
 DDM_TIME_INSTANTIATE(64)
 DDM_TIME_INSTANTIATE(128)
+DDM_TIME_INSTANTIATE(192)
 }  // namespace ddm

@@ -156,6 +156,12 @@ __device__ __forceinline__ int64_t time_q0(int64_t id) {
 template <int L>
 constexpr bool time_prefetch() { return L <= 1024; }
 
+// Transform lengths: 2^k (16 <= L <= 8192, E = 16 or 8) and 3 * 2^k
+// (192 <= L <= 6144, E = 12: radix-4 and radix-2 passes, then one radix-3
+// pass; E = 24 would hold too many registers), so that the zero-padded length
+// 2 L >= 2 N - 1 exceeds 2 N by at most a factor 4/3 instead of 2.
+constexpr bool time_len_3(int L) { return L % 3 == 0; }
+
 template <int L, int QPW, int QB, int E, bool FULL, bool F16>
 __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__ spec, int64_t nq,
                                                        int N, int M, const float2* __restrict__ twN2,
@@ -304,13 +310,23 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
         sr[i] = a.x + b.x;
         si[i] = a.y + b.y;
       }
+      if constexpr (((E / 2) & (E / 2 - 1)) == 0) {
 #pragma unroll
-      for (int w = E / 4; w > 0; w >>= 1)
+        for (int w = E / 4; w > 0; w >>= 1)
 #pragma unroll
-        for (int i = 0; i < w; ++i) {
-          sr[i] += sr[i + w];
-          si[i] += si[i + w];
-        }
+          for (int i = 0; i < w; ++i) {
+            sr[i] += sr[i + w];
+            si[i] += si[i + w];
+          }
+      } else {  // E / 2 not a power of two: fold the upper half onto the lower until one is left
+#pragma unroll
+        for (int n = E / 2; n > 1; n -= n / 2)
+#pragma unroll
+          for (int i = 0; i < n / 2; ++i) {
+            sr[i] += sr[n - 1 - i];
+            si[i] += si[n - 1 - i];
+          }
+      }
       const float inv_n = 1.0f / (float)N;
       mr = group_sum<T>(sr[0], tid, scratchf) * inv_n;
       mi = group_sum<T>(si[0], tid, scratchf) * inv_n;
@@ -392,7 +408,7 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
     // ---- D(m) = (S(N-m) + S(N) - S(m) - 2 Re c(m)) / (N-m) ----
     if (qd >= 0) {
       const double sN = xd[LdsView<1, true>::slot(N)];
-      const float inv_l = 1.0f / (float)L;  // 2 / N2, exact
+      const float inv_l = 1.0f / (float)L;  // 2 / N2 (exact for L a power of two)
       float* drow = D + (size_t)qd * M;
       // With T a multiple of 16, the padded slots of m = tid + e T, N - m and
       // L - m (for e >= 1, where L - m >= 1) are a per-thread slot plus or
@@ -407,7 +423,7 @@ __global__ void __launch_bounds__(QPW * (L / E)) k_time(const void* __restrict__
         if (FULL || m < M) {
           const int set = LdsView<1, true>::slot(e * T);
           const float2 zm = v[e];
-          const float2 zr = (LIN && e > 0) ? yb.base[s_lm - set] : yb[(L - m) & (L - 1)];
+          const float2 zr = (LIN && e > 0) ? yb.base[s_lm - set] : yb[m == 0 ? 0 : L - m];
           const float2 w = w_n(m);  // (cos th, -sin th), th = 2 pi m / N2
           // 2 Re c(m) = (2/N2) Re sum_k P_k e^{2 pi i k m / N2}
           const float two_c = 0.5f * ((zm.x + zr.x) + w.x * (zm.y + zr.y) - w.y * (zm.x - zr.x)) * inv_l;
@@ -434,6 +450,7 @@ inline int env_int(const char* name) {
 }
 
 inline int time_e(int L) {
+  if (time_len_3(L)) return 12;
   static const int env = env_int("DDM_TIME_E");
   if ((env == 8 || env == 16) && L / env >= 1 && L % env == 0 && L >= 16) return env;
   return 16;
@@ -443,9 +460,9 @@ inline int time_qpw(int L, int E) {
   static const int env = env_int("DDM_TIME_QPW");
   int qpw;
   if (L <= 256) qpw = 16;
-  else if (L == 512) qpw = 8;
-  else if (L == 1024) qpw = 4;
-  else if (L == 2048) qpw = 2;
+  else if (L <= 512) qpw = 8;
+  else if (L <= 1024) qpw = 4;
+  else if (L <= 2048) qpw = 2;
   else qpw = 1;
   if (env == 1 || env == 2 || env == 4 || env == 8 || env == 16) qpw = env;
   while (qpw > 1 && (qpw * (L / E) > 1024 || time_lds_bytes(L, qpw) > 160 * 1024))
@@ -541,14 +558,20 @@ template <int L, int QB>
 hipError_t time_e_go(hipStream_t s, const void* spec, int64_t nq, int N, int M,
                             const float2* tw, const double* ramp, const int32_t* qmap, const int32_t* qexp, float* D,
                             TimeShape shape) {
-  const int E = (shape.E == 8 || shape.E == 16) ? shape.E : time_e(L);
-  int qpw = shape.qpw > 0 ? shape.qpw : time_qpw(L, E);
-  while (qpw > 1 && (qpw * (L / E) > 1024 || time_lds_bytes(L, qpw) > 160 * 1024))
-    qpw >>= 1;
-  if constexpr (L >= 512) {
-    if (E == 8) return time_qpw_go<L, QB, 8>(s, qpw, spec, nq, N, M, tw, ramp, qmap, qexp, D);
+  if constexpr (time_len_3(L)) {
+    int qpw = shape.qpw > 0 ? shape.qpw : time_qpw(L, 12);
+    while (qpw > 1 && (qpw * (L / 12) > 1024 || time_lds_bytes(L, qpw) > 160 * 1024)) qpw >>= 1;
+    return time_qpw_go<L, QB, 12>(s, qpw, spec, nq, N, M, tw, ramp, qmap, qexp, D);
+  } else {
+    const int E = (shape.E == 8 || shape.E == 16) ? shape.E : time_e(L);
+    int qpw = shape.qpw > 0 ? shape.qpw : time_qpw(L, E);
+    while (qpw > 1 && (qpw * (L / E) > 1024 || time_lds_bytes(L, qpw) > 160 * 1024))
+      qpw >>= 1;
+    if constexpr (L >= 512) {
+      if (E == 8) return time_qpw_go<L, QB, 8>(s, qpw, spec, nq, N, M, tw, ramp, qmap, qexp, D);
+    }
+    return time_qpw_go<L, QB, 16>(s, qpw, spec, nq, N, M, tw, ramp, qmap, qexp, D);
   }
-  return time_qpw_go<L, QB, 16>(s, qpw, spec, nq, N, M, tw, ramp, qmap, qexp, D);
 }
 
 // Every launch of the time kernel for one transform length L (blocked or

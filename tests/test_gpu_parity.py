@@ -77,20 +77,22 @@ def test_step_one_spectra(gpu, precondition):
     assert err < 2e-6
 
 
-@pytest.mark.parametrize("N", [2, 3, 5, 17, 100, 1000, 1537, 2048, 3000, 4096])
-def test_step_two_from_spectra(gpu, N):
-    say("case: step two N =", N)
+@pytest.mark.parametrize("padding", ["pow2", "minimal"])
+@pytest.mark.parametrize("N", [2, 3, 5, 17, 100, 150, 192, 300, 384, 700, 768, 1000, 1200, 1536, 1537, 2048, 2500,
+                               3000, 3072, 4096, 5000, 8192])
+def test_step_two_from_spectra(gpu, N, padding):
+    say("case: step two N =", N, padding)
     r = np.random.default_rng(N)
     Q = 37
     F = (r.standard_normal((Q, N)) + 1j * r.standard_normal((Q, N))).astype(np.complex64)
     F += np.complex64(20 + 5j)  # a static offset per q
-    plan = gpu.Plan(16, 16, N, k2_max=40)  # step two only uses the plan's n_q and N
+    plan = gpu.Plan(16, 16, N, k2_max=40, padding=padding)  # step two only uses the plan's n_q and N
     nq = plan.n_q
     Fx = np.resize(F, (nq, N)).astype(np.complex64)
     Dg = plan.structure_from_spectra(torch.from_numpy(Fx).cuda()).cpu().numpy()
     Do = structure.structure_function_direct(Fx.astype(np.complex128))
     e = per_q_error(Dg, Do)
-    say("N", N, describe(e))
+    say("N", N, padding, describe(e))
     assert e.max() <= TOL_F32
 
 
