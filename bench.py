@@ -165,10 +165,12 @@ def learned_leg(log):
         (t1 - t0, t2 - t1, losses[0], losses[-1]))
     return {"stack": "1024x1024 uint16 x 2048 frames, D0 %.3g px^2/frame, SNR %.3g, seed 7" % (D0, snr),
             "n_curves": res["n"], "K": 64,
-            "lm_default_ms": res["default_ms"], "mlp_plus_lm_ms": res["learned_ms"],
-            "mlp_plus_lm_refit_ms": res["learned_refit_ms"],
+            "lm_default_ms": res["default_ms"], "mlp_ms": res["mlp_ms"], "mlp_plus_lm_ms": res["learned_ms"],
+            "mlp_plus_lm_refit_ms": res["learned_refit_ms"], "mlp_plus_lm_gated_ms": res["learned_gated_ms"],
             "learned": "start from the lower-cost of the network's and the default start, one fit; "
-                       "learned_refit: network start, refit from the default start if not converged",
+                       "learned_refit: network start, refit from the default start if not converged; "
+                       "learned_gated: network start where its tau is within [m_1/4, 4 m_K], else the "
+                       "default start, one fit",
             "all": res["all"], "measurable_tau_2_to_512": res.get("measurable"),
             "training": {"curves": args.learned_curves, "epochs": args.learned_epochs,
                          "final_loss": losses[-1], "data_s": t1 - t0, "train_s": t2 - t1}}

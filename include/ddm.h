@@ -273,7 +273,7 @@ enum {
   DDM_FIT_NONFINITE = 4,  /* non-finite data or parameters */
   DDM_FIT_STALLED = 8,    /* no decreasing step found, not stationary */
   DDM_FIT_FALLBACK = 16,  /* refitted from the default start after failing from the given one */
-  DDM_FIT_DEFAULT_START = 32 /* fallback 2: the default start had the lower cost and was used */
+  DDM_FIT_DEFAULT_START = 32 /* fallback 2 or 3: the default start was used */
 };
 
 /* Sample rows of D at K fractional lags: linear interpolation between the two
@@ -291,7 +291,10 @@ typedef struct ddm_fit_desc {
   int32_t max_iter;     /* Jacobian evaluations per curve (default 200) */
   int32_t fallback;     /* with init_dev: 0 fit from it; 1 curves not converged from it are refitted
                            from the default start; 2 each curve starts from whichever of init_dev and
-                           the default start has the lower cost (one fit, no refit) */
+                           the default start has the lower cost (one fit, no refit); 3 each curve
+                           starts from init_dev when its tau lies within [m_1 / 4, 4 m_K] and its A
+                           is at least 5% of |A| + |B| (a decay the sampled lags resolve), else from
+                           the default start (one fit) */
   double lambda0;       /* initial Marquardt damping (default 1e-3) */
   double ftol;          /* stop when an accepted step lowers the cost by <= ftol * cost (1e-7) */
   double xtol;          /* stop when |step| <= xtol (|p| + xtol), p = (A, B, log tau) (1e-7) */

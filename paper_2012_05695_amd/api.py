@@ -293,7 +293,9 @@ def fit(curves, lags, init=None, fallback=True, max_iter=200, ftol=1e-7, xtol=1e
     init: optional [n, 3] float32 (A, B, log tau) start; else the default start.
     fallback (with init): True refits from the default start the curves that do
     not converge; "best" starts each curve from whichever of init and the default
-    start has the lower cost; False fits from init only.
+    start has the lower cost; "gate" starts from init where its tau lies within
+    [m_1 / 4, 4 m_K] and its A is at least 5% of |A| + |B|, else from the default
+    start; False fits from init only.
     """
     lags = np.ascontiguousarray(np.asarray(lags, dtype=np.float32))
     n, K = curves.shape
@@ -303,7 +305,8 @@ def fit(curves, lags, init=None, fallback=True, max_iter=200, ftol=1e-7, xtol=1e
     d = L.FitDesc()
     _lib.ddm_fit_desc_init(ctypes.byref(d))
     d.K, d.max_iter = K, int(max_iter)
-    d.fallback = 2 if fallback == "best" else (1 if fallback else 0)
+    d.fallback = {"best": 2, "gate": 3}.get(fallback, 1 if fallback is True else 0) \
+        if isinstance(fallback, (str, bool)) else int(fallback)
     d.ftol, d.xtol, d.gtol, d.lambda0 = float(ftol), float(xtol), float(gtol), float(lambda0)
     with torch.cuda.device(curves.device):
         d.stream = _stream_handle(stream).value

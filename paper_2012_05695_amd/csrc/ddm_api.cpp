@@ -977,9 +977,9 @@ ddm_status ddm_fit(const ddm_fit_desc* f, const float* curves, const float* lags
   if (f->max_iter < 1) return fail(DDM_ERR_INVALID_ARGUMENT, "max_iter must be >= 1");
   if (!(f->lambda0 > 0) || !(f->ftol >= 0) || !(f->xtol >= 0) || !(f->gtol >= 0))
     return fail(DDM_ERR_INVALID_ARGUMENT, "lambda0 must be > 0 and tolerances >= 0");
-  if (f->fallback < 0 || f->fallback > 2) return fail(DDM_ERR_INVALID_ARGUMENT, "fallback must be 0, 1 or 2");
+  if (f->fallback < 0 || f->fallback > 3) return fail(DDM_ERR_INVALID_ARGUMENT, "fallback must be 0, 1, 2 or 3");
   const bool fb = init != nullptr && f->fallback == 1;
-  const bool best = init != nullptr && f->fallback == 2;
+  const int start_mode = init == nullptr ? 0 : (f->fallback == 2 ? 1 : (f->fallback == 3 ? 2 : 0));
   if (fb && flags == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "fallback needs flags_dev");
   LagSet ls;
   ddm_status st = fill_lags(lags, f->K, 1e-30f, 3.0e38f, &ls);
@@ -993,7 +993,7 @@ ddm_status ddm_fit(const ddm_fit_desc* f, const float* curves, const float* lags
   prm.exact_fit = 1e-12;  // relative cost floor of FP32 residuals
   prm.max_iter = f->max_iter;
   hipStream_t s = (hipStream_t)f->stream;
-  hipError_t e = launch_lm(s, curves, n, ls, init, prm, nullptr, params, iters, flags, best);
+  hipError_t e = launch_lm(s, curves, n, ls, init, prm, nullptr, params, iters, flags, start_mode);
   if (e == hipSuccess && fb) e = launch_lm(s, curves, n, ls, nullptr, prm, flags, params, iters, flags);
   if (e != hipSuccess) return hip_fail(e, "fit launch");
   return DDM_OK;

@@ -152,6 +152,6 @@ hipError_t launch_sample(hipStream_t s, const float* D, int64_t n, int M, const 
 
 hipError_t launch_lm(hipStream_t s, const float* Y, int64_t n, const LagSet& lags, const float* init,
                      const LmParams& prm, const int32_t* only_if_flag_clear, float* params,
-                     int32_t* iters, int32_t* flags, bool best_start = false);
+                     int32_t* iters, int32_t* flags, int start_mode = 0);
 
 }  // namespace ddm

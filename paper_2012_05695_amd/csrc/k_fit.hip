@@ -59,13 +59,16 @@ __device__ __forceinline__ double lm_cost(const float (&y)[K], const LagSet& lag
   return c;
 }
 
-// best_start: with init given, start from whichever of init and the default
-// start has the lower cost (LM_FLAG_DEFAULT_START when the default wins).
+// start_mode with init given: 0 start from init; 1 from whichever of init and
+// the default start has the lower cost; 2 from init when its tau lies within
+// [m_1 / 4, 4 m_K] and its A is at least 5% of |A| + |B| (a decay the sampled
+// lags can resolve), else from the default start.  LM_FLAG_DEFAULT_START when
+// the default start is used.
 __global__ void __launch_bounds__(64) k_lm(const float* __restrict__ Y, int64_t n, LagSet lags,
                                            const float* __restrict__ init, LmParams prm,
                                            const int32_t* only_if_flag_clear,  // may alias flags
                                            float* __restrict__ params, int32_t* iters,
-                                           int32_t* flags, int best_start) {
+                                           int32_t* flags, int start_mode) {
   constexpr int K = kMaxK;
   __shared__ float tile[64 * (K + 1)];
   const int64_t c0 = (int64_t)blockIdx.x * 64;
@@ -100,9 +103,15 @@ __global__ void __launch_bounds__(64) k_lm(const float* __restrict__ Y, int64_t 
   if (init != nullptr && only_if_flag_clear == nullptr) {
     const double Ai = init[cid * 3 + 0], Bi = init[cid * 3 + 1], thi = init[cid * 3 + 2];
     bool take = true;
-    if (best_start) {
+    if (start_mode == 1) {
       const double ci = lm_cost<K>(y, lags, k, Ai, Bi, thi), cd = lm_cost<K>(y, lags, k, A, B, th);
       take = isfinite(ci) && !(cd < ci);  // ties go to the given start
+    } else if (start_mode == 2) {
+      // a decay the sampled lags can resolve: tau inside the window and an
+      // amplitude of at least 5% of the curve (below it the curve is noise)
+      const double ln4 = 1.3862943611198906;
+      take = thi >= log((double)lags.m[0]) - ln4 && thi <= log((double)lags.m[k - 1]) + ln4 &&
+             Ai >= 0.05 * (fabs(Ai) + fabs(Bi));
     }
     if (take) {
       A = Ai;
@@ -207,10 +216,10 @@ hipError_t launch_sample(hipStream_t s, const float* D, int64_t n, int M, const 
 
 hipError_t launch_lm(hipStream_t s, const float* Y, int64_t n, const LagSet& lags, const float* init,
                      const LmParams& prm, const int32_t* only_if_flag_clear, float* params,
-                     int32_t* iters, int32_t* flags, bool best_start) {
+                     int32_t* iters, int32_t* flags, int start_mode) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_lm, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, Y, n, lags, init, prm,
-                     only_if_flag_clear, params, iters, flags, best_start ? 1 : 0);
+                     only_if_flag_clear, params, iters, flags, start_mode);
   return hipGetLastError();
 }
 

@@ -43,24 +43,55 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const __bf16*
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 
+  // unit stride along k with 16-byte aligned rows: each thread moves 8
+  // consecutive k at once (one 16-byte load per operand and k step)
+  const bool vecA = sak == 1 && (sam % 8) == 0 && (((uintptr_t)A) & 15) == 0;
+  const bool vecB = sbk == 1 && (sbn % 8) == 0 && (((uintptr_t)B) & 15) == 0;
+  static_assert(TM * TK / 8 == 256 && TN * TK / 8 == 256, "one 8-element chunk per thread");
   for (int k0 = 0; k0 < K; k0 += TK) {
     // tile loads, zero outside the matrices; the index order follows the
     // unit-stride dimension so that neighbouring threads read neighbouring bytes
+    if (vecA) {
+      const int i = threadIdx.x / (TK / 8), kc = 8 * (threadIdx.x % (TK / 8));
+      const int gi = i0 + i, gk = k0 + kc;
+      bf16x8 v;
+      if (gi < M && gk + 8 <= K) {
+        v = *reinterpret_cast<const bf16x8*>(A + (int64_t)gi * sam + gk);
+      } else {
 #pragma unroll
-    for (int s = 0; s < (TM * TK) / 256; ++s) {
-      const int f = threadIdx.x + s * 256;
-      int i, k;
-      if (sak == 1) { i = f / TK; k = f % TK; } else { i = f % TM; k = f / TM; }
-      const int gi = i0 + i, gk = k0 + k;
-      As[i * AS + k] = (gi < M && gk < K) ? A[gi * sam + gk * sak] : (__bf16)0.0f;
+        for (int t = 0; t < 8; ++t) v[t] = (gi < M && gk + t < K) ? A[(int64_t)gi * sam + gk + t] : (__bf16)0.0f;
+      }
+      *reinterpret_cast<bf16x8*>(&As[i * AS + kc]) = v;
+    } else {
+#pragma unroll
+      for (int s = 0; s < (TM * TK) / 256; ++s) {
+        const int f = threadIdx.x + s * 256;
+        int i, k;
+        if (sak == 1) { i = f / TK; k = f % TK; } else { i = f % TM; k = f / TM; }
+        const int gi = i0 + i, gk = k0 + k;
+        As[i * AS + k] = (gi < M && gk < K) ? A[gi * sam + gk * sak] : (__bf16)0.0f;
+      }
     }
+    if (vecB) {
+      const int j = threadIdx.x / (TK / 8), kc = 8 * (threadIdx.x % (TK / 8));
+      const int gj = j0 + j, gk = k0 + kc;
+      bf16x8 v;
+      if (gj < N && gk + 8 <= K) {
+        v = *reinterpret_cast<const bf16x8*>(B + (int64_t)gj * sbn + gk);
+      } else {
 #pragma unroll
-    for (int s = 0; s < (TN * TK) / 256; ++s) {
-      const int f = threadIdx.x + s * 256;
-      int j, k;
-      if (sbk == 1) { j = f / TK; k = f % TK; } else { j = f % TN; k = f / TN; }
-      const int gj = j0 + j, gk = k0 + k;
-      Bt[j * AS + k] = (gj < N && gk < K) ? B[gk * sbk + gj * sbn] : (__bf16)0.0f;
+        for (int t = 0; t < 8; ++t) v[t] = (gj < N && gk + t < K) ? B[(int64_t)gj * sbn + gk + t] : (__bf16)0.0f;
+      }
+      *reinterpret_cast<bf16x8*>(&Bt[j * AS + kc]) = v;
+    } else {
+#pragma unroll
+      for (int s = 0; s < (TN * TK) / 256; ++s) {
+        const int f = threadIdx.x + s * 256;
+        int j, k;
+        if (sbk == 1) { j = f / TK; k = f % TK; } else { j = f % TN; k = f / TN; }
+        const int gj = j0 + j, gk = k0 + k;
+        Bt[j * AS + k] = (gj < N && gk < K) ? B[gk * sbk + gj * sbn] : (__bf16)0.0f;
+      }
     }
     __syncthreads();
 #pragma unroll

@@ -75,8 +75,9 @@ static ddm_status check_mlp(ddm_mlp_t n) {
   return DDM_OK;
 }
 
-// Forward over B rows already converted into n->xb; fills z, h, y.
-static hipError_t forward_rows(ddm_mlp_s* n, int64_t B) {
+// Forward over B rows already converted into n->xb; fills h and y (= out when
+// given), and the pre-activations z when keep_z (the backward pass needs them).
+static hipError_t forward_rows(ddm_mlp_s* n, int64_t B, bool keep_z = true, float* out = nullptr) {
   hipStream_t s = n->stream;
   const __bf16* in = n->xb;
   int64_t kin = NIN;
@@ -84,13 +85,13 @@ static hipError_t forward_rows(ddm_mlp_s* n, int64_t B) {
   for (int l = 0; l < 3; ++l) {
     // Z = H_in W^T + b : A = H_in [B][kin], B(k, j) = W[j][k]
     hipError_t e = launch_gemm(s, EPI_BIAS_GELU, (int)B, NH, (int)kin, in, kin, 1, n->pb + ow[l], 1, kin,
-                               n->p + ob[l], n->z[l], NH, n->h[l], NH, nullptr, 0);
+                               n->p + ob[l], keep_z ? n->z[l] : nullptr, NH, n->h[l], NH, nullptr, 0);
     if (e != hipSuccess) return e;
     in = n->h[l];
     kin = NH;
   }
-  return launch_gemm(s, EPI_BIAS, (int)B, NOUT, NH, in, NH, 1, n->pb + OW4, 1, NH, n->p + OB4, n->y, NOUT,
-                     nullptr, 0, nullptr, 0);
+  return launch_gemm(s, EPI_BIAS, (int)B, NOUT, NH, in, NH, 1, n->pb + OW4, 1, NH, n->p + OB4, out ? out : n->y,
+                     NOUT, nullptr, 0, nullptr, 0);
 }
 
 // Gradient of the mean squared error of the last forward against T [B][3].
@@ -260,8 +261,7 @@ ddm_status ddm_mlp_forward(ddm_mlp_t n, const float* x, int64_t rows, float* y) 
   for (int64_t r0 = 0; r0 < rows; r0 += n->max_batch) {
     const int64_t B = std::min<int64_t>(n->max_batch, rows - r0);
     hipError_t e = launch_to_bf16(n->stream, x + r0 * NIN, n->xb, B * NIN);
-    if (e == hipSuccess) e = forward_rows(n, B);
-    if (e == hipSuccess) e = hipMemcpyAsync(y + r0 * NOUT, n->y, B * NOUT * 4, hipMemcpyDeviceToDevice, n->stream);
+    if (e == hipSuccess) e = forward_rows(n, B, false, y + r0 * NOUT);
     if (e != hipSuccess) return hipf(e, "mlp forward");
   }
   return DDM_OK;

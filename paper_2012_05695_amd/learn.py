@@ -114,7 +114,8 @@ class Initialiser:
         s = std.detach().cpu().numpy().astype(np.float64)
         p[_OW4:_OB4] = (p[_OW4:_OB4].reshape(3, 256) * s[:, None]).ravel()
         p[_OB4:_OB4 + 3] = p[_OB4:_OB4 + 3] * s + m
-        self.net = api.Mlp(seed=0, max_batch=net.max_batch, device=net.device)
+        # inference runs over whole stacks: large batches, few launches
+        self.net = api.Mlp(seed=0, max_batch=max(net.max_batch, 1 << 17), device=net.device)
         self.net.set_params(p.astype(np.float32))
 
     def init(self, curves):
@@ -149,24 +150,31 @@ def train(X, T, epochs=40, batch=4096, lr=1e-3, seed=0, log=None):
 def compare(curves, lags, init, truth_tau=None, tau_window=None):
     """Fit every curve from the default start and from the learned one.
 
-    Two ways to use the learned start: "learned" starts each curve from
+    Three ways to use the learned start: "learned" starts each curve from
     whichever of the network's start and the default start has the lower cost
     (one fit); "learned_refit" starts from the network's start and refits from
-    the default start the curves that do not converge.  Returns device times
-    (the learned times include the network) and, per subset ("all", and with
-    ground truth "measurable" = true tau inside tau_window), the mean
-    iterations, converged fraction, median |log tau - log tau_true| and the
-    fraction of curves whose final cost is not worse than from the default start."""
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    the default start the curves that do not converge; "learned_gated" starts
+    from the network's start where its tau lies within [m_1 / 4, 4 m_K] and its
+    A is at least 5% of |A| + |B|, from the default start elsewhere (one fit).  Returns device times (the
+    learned times include the network; "mlp_ms" is the network alone) and, per
+    subset ("all", and with ground truth "measurable" = true tau inside
+    tau_window), the mean iterations, converged fraction, median
+    |log tau - log tau_true| and the fraction of curves whose final cost is not
+    worse than from the default start."""
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
     ev[0].record()
     p0, i0, f0 = api.fit(curves, lags)
     ev[1].record()
     y = init.init(curves)
-    p1, i1, f1 = api.fit(curves, lags, init=y, fallback="best")
     ev[2].record()
+    p1, i1, f1 = api.fit(curves, lags, init=y, fallback="best")
+    ev[3].record()
     y = init.init(curves)
     p2, i2, f2 = api.fit(curves, lags, init=y, fallback=True)
-    ev[3].record()
+    ev[4].record()
+    y = init.init(curves)
+    p3, i3, f3 = api.fit(curves, lags, init=y, fallback="gate")
+    ev[5].record()
     torch.cuda.synchronize()
     lags64 = torch.from_numpy(lags.astype(np.float64)).to(curves.device)
 
@@ -176,22 +184,24 @@ def compare(curves, lags, init, truth_tau=None, tau_window=None):
         return (r * r).sum(dim=1)
 
     c0 = cost(p0)
-    costs = {"learned": cost(p1), "learned_refit": cost(p2)}
+    costs = {"learned": cost(p1), "learned_refit": cost(p2), "learned_gated": cost(p3)}
     subsets = {"all": torch.ones(curves.shape[0], dtype=torch.bool, device=curves.device)}
     t = None
     if truth_tau is not None:
         t = torch.from_numpy(np.asarray(truth_tau, dtype=np.float64)).to(curves.device)
         subsets["measurable"] = (t > tau_window[0]) & (t < tau_window[1])
     out = {"n": int(curves.shape[0]), "default_ms": ev[0].elapsed_time(ev[1]),
-           "learned_ms": ev[1].elapsed_time(ev[2]), "learned_refit_ms": ev[2].elapsed_time(ev[3])}
+           "mlp_ms": ev[1].elapsed_time(ev[2]), "learned_ms": ev[1].elapsed_time(ev[3]),
+           "learned_refit_ms": ev[3].elapsed_time(ev[4]), "learned_gated_ms": ev[4].elapsed_time(ev[5])}
     for name, sel in subsets.items():
         if not bool(sel.any()):
             continue
         rec = {"n": int(sel.sum())}
-        for key, p, it, fl in (("default", p0, i0, f0), ("learned", p1, i1, f1), ("learned_refit", p2, i2, f2)):
+        for key, p, it, fl in (("default", p0, i0, f0), ("learned", p1, i1, f1), ("learned_refit", p2, i2, f2),
+                               ("learned_gated", p3, i3, f3)):
             r = {"mean_iters": float(it[sel].float().mean()),
                  "converged": float(((fl[sel] & 1) != 0).float().mean())}
-            if key == "learned":
+            if key in ("learned", "learned_gated"):
                 r["default_start_chosen"] = float(((fl[sel] & 32) != 0).float().mean())
             if key == "learned_refit":
                 r["refitted"] = float(((fl[sel] & 16) != 0).float().mean())

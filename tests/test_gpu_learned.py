@@ -24,11 +24,13 @@ def test_learned_start_beats_default(gpu):
     res = learn.compare(curves, lags, init, truth_tau=tau, tau_window=(2.0, 128.0))
     print(res, flush=True)
     m, a = res["measurable"], res["all"]
-    for key in ("learned", "learned_refit"):
+    for key in ("learned", "learned_refit", "learned_gated"):
         assert m[key]["mean_iters"] < 0.9 * m["default"]["mean_iters"]
         assert m[key]["converged"] >= m["default"]["converged"] - 0.005
         assert m[key]["cost_not_worse"] >= 0.97
-    # refitting the failures keeps every curve the default start converges
+    # refitting the failures keeps every curve the default start converges, and
+    # so does the gated start (the default start wherever tau is not resolvable)
     assert a["learned_refit"]["converged"] >= a["default"]["converged"] - 0.005
+    assert a["learned_gated"]["converged"] >= a["default"]["converged"] - 0.005
     # the lower-cost start with one fit costs about one fit more than the network
     assert res["learned_ms"] < res["learned_refit_ms"]
