@@ -469,10 +469,43 @@ def main():
                         "saturated_values": int(plan16.fp16_saturations())}
     plan16.status()
     plan16.close()
+    out["host_frames"] = host_frames_leg(plan, frames, D, args.steps)
     del frames, D
     plan.close()
     torch.cuda.empty_cache()
     finish(args, out, frames_cpu, nq)
+
+
+def host_frames_leg(plan, frames, D, steps):
+    """The same workload with the frames in pinned host memory
+    (ddm_structure_function_host): the PCIe-inclusive rate, beside a plain
+    host-to-device copy of the frames."""
+    import torch
+    N, H, W = frames.shape
+    pinned = frames.cpu().pin_memory()
+    fb = H * W * pinned.element_size()
+    staging = torch.empty(((fb + 255) // 256) * 256 + 2 * 64 * fb + 512, dtype=torch.uint8, device="cuda")
+    plan.structure_function_host(pinned, staging, out=D)
+    dev = torch.empty_like(frames)
+    dev.copy_(pinned, non_blocking=True)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    reps = max(3, steps // 4)
+    ev[0].record()
+    for _ in range(reps):
+        plan.structure_function_host(pinned, staging, out=D)
+    ev[1].record()
+    for _ in range(reps):
+        dev.copy_(pinned, non_blocking=True)
+    ev[2].record()
+    torch.cuda.synchronize()
+    plan.status()
+    t_h = ev[0].elapsed_time(ev[1]) / reps
+    t_c = ev[1].elapsed_time(ev[2]) / reps
+    del dev, staging
+    return {"ms_per_stack": t_h, "frames_per_s": N / (t_h * 1e-3), "h2d_copy_ms": t_c,
+            "h2d_GBs": pinned.numel() * pinned.element_size() / (t_c * 1e-3) / 1e9,
+            "work": "structure function only (no bins), frames in pinned host memory, 2 x 64-frame staging"}
 
 
 def finish(args, out, frames_cpu, nq):

@@ -152,6 +152,22 @@ ddm_status ddm_structure_function(ddm_plan_t plan, const void* frames_dev, float
  * (for testing the reporting path). */
 ddm_status ddm_plan_status(ddm_plan_t plan);
 
+/* Frames resident in host memory (a camera or file reader's buffers; the
+ * paper's memory-IO share of step one): frames_host [N][H][W] as in
+ * ddm_structure_function but in host memory, pinned (hipHostMalloc or a pinned
+ * torch tensor) for the copies to overlap the transforms (pageable memory
+ * works, without overlap).  staging_dev: caller-owned device memory of
+ * staging_bytes (256-byte aligned, at least frame 0 plus two frames,
+ * align256(H W b) + 2 H W b): frame 0 is copied once, then batches of frames
+ * alternate between two halves of the rest on a copy stream while the
+ * previous batch is transformed (two-kernel step one).  Requires the plan's
+ * workspace; each group of wave vectors (Appendix C) copies the frames again.
+ * D_dev as ddm_structure_function, bit-identical to it.  FP32 spectrum store
+ * only (DDM_ERR_UNSUPPORTED otherwise, and inside a graph capture).  The host
+ * memory must stay valid until the call's work has completed. */
+ddm_status ddm_structure_function_host(ddm_plan_t plan, const void* frames_host, void* staging_dev,
+                                       size_t staging_bytes, float* D_dev);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * result as ddm_structure_function, bit for bit, with the library's own

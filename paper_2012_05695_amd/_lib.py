@@ -100,6 +100,7 @@ SIGNATURES = [
     ("ddm_plan_set_workspace", c_int32, [c_void_p, c_void_p, c_size_t]),
     ("ddm_structure_function", c_int32, [c_void_p, c_void_p, c_void_p]),
     ("ddm_structure_function_noalloc", c_int32, [c_void_p, c_void_p, c_void_p]),
+    ("ddm_structure_function_host", c_int32, [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("ddm_image_spectra", c_int32, [c_void_p, c_void_p, c_void_p]),
     ("ddm_structure_from_spectra", c_int32, [c_void_p, c_void_p, c_void_p]),
     ("ddm_radial_average", c_int32,

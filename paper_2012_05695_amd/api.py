@@ -194,6 +194,29 @@ class Plan:
                                                                   ctypes.c_void_p(out.data_ptr())))
         return out
 
+    def structure_function_host(self, frames_host, staging, out=None):
+        """D from frames in host memory (a CPU tensor, pinned for overlapped
+        copies) through the device staging buffer `staging` (uint8 tensor;
+        ddm_structure_function_host).  The frames must stay alive until the
+        stream has passed the call."""
+        if not isinstance(frames_host, torch.Tensor) or frames_host.device.type != "cpu":
+            raise ValueError("frames_host must be a CPU tensor")
+        if frames_host.dtype not in _PIX_DTYPES[self.pixel] or \
+                tuple(frames_host.shape) != (self.n_frames, self.height, self.width) or \
+                not frames_host.is_contiguous():
+            raise ValueError("frames_host must be a contiguous [N, H, W] tensor of the plan's pixel type")
+        _require(staging, "staging", (torch.uint8,), (staging.numel(),), self.device)
+        if self._ws is None:
+            self.allocate_workspace()
+        if out is None:
+            out = torch.empty((self.n_q, self.max_lag), dtype=torch.float32, device="cuda:%d" % self.device)
+        _require(out, "D", (torch.float32,), (self.n_q, self.max_lag), self.device)
+        with torch.cuda.device(self.device):
+            _check(_lib.ddm_structure_function_host(self._h, ctypes.c_void_p(frames_host.data_ptr()),
+                                                    ctypes.c_void_p(staging.data_ptr()), staging.numel(),
+                                                    ctypes.c_void_p(out.data_ptr())))
+        return out
+
     def structure_function_noalloc(self, frames, out=None):
         """As structure_function, on the library's static device scratch instead
         of a workspace (ddm_structure_function_noalloc): no device allocation

@@ -80,6 +80,11 @@ struct ddm_plan_s {
   size_t frame_inter_bytes;
   int fb_target;
   hipStream_t stream;
+  // host-resident frames (ddm_structure_function_host): copies on s_copy into
+  // two staging halves; events: a half's frames arrived, a half's frames read,
+  // the plan's stream reached the call
+  hipStream_t s_copy;
+  hipEvent_t ev_h2d[2], ev_used[2], ev_start;
   // device tables (one allocation)
   void* dev_tables;
   float2 *twW, *twH, *twT;
@@ -424,6 +429,19 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
     }
     std::memset(p->rb_host, 0, 2 * kReadback * sizeof(int32_t));
   }
+  p->s_copy = nullptr;
+  p->ev_start = nullptr;
+  for (int i = 0; i < 2; ++i) p->ev_h2d[i] = p->ev_used[i] = nullptr;
+  e = hipStreamCreateWithFlags(&p->s_copy, hipStreamNonBlocking);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    e = hipEventCreateWithFlags(&p->ev_h2d[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_used[i], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_start, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    ddm_plan_destroy(p);
+    return hip_fail(e, "copy stream setup");
+  }
   *out = p;
   g_err.clear();
   return DDM_OK;
@@ -433,7 +451,14 @@ ddm_status ddm_plan_destroy(ddm_plan_t p) {
   if (p == nullptr) return DDM_OK;
   if (p->magic != kPlanMagic) return fail(DDM_ERR_STATE, "plan handle is not a live plan");
   hipStreamSynchronize(p->stream);
+  if (p->s_copy) hipStreamSynchronize(p->s_copy);
   prof_drain(p);
+  for (int i = 0; i < 2; ++i) {
+    if (p->ev_h2d[i]) hipEventDestroy(p->ev_h2d[i]);
+    if (p->ev_used[i]) hipEventDestroy(p->ev_used[i]);
+  }
+  if (p->ev_start) hipEventDestroy(p->ev_start);
+  if (p->s_copy) hipStreamDestroy(p->s_copy);
   for (int i = 0; i < kReadback; ++i)
     if (p->rb_ev[i]) hipEventDestroy(p->rb_ev[i]);
   if (p->rb_host) hipHostFree(p->rb_host);
@@ -776,6 +801,92 @@ ddm_status ddm_structure_function_noalloc(ddm_plan_t p, const void* frames, floa
   p->ws = ws;
   p->ws_bytes = ws_bytes;
   return st;
+}
+
+// ---------------------------------------------------------------------------
+// Frames resident in host memory: batches of frames go to the device through
+// two staging halves on a copy stream while the row and column transforms of
+// the previous batch run; frame 0 (the preconditioning reference) has a slot
+// of its own.  Every group of wave vectors streams the frames again (the
+// paper's group execution, Appendix C, with the frames re-read from the host).
+// ---------------------------------------------------------------------------
+ddm_status ddm_structure_function_host(ddm_plan_t p, const void* frames_host, void* staging, size_t staging_bytes,
+                                       float* D) {
+  ddm_status st = check_plan(p);
+  if (st != DDM_OK) return st;
+  if (frames_host == nullptr || staging == nullptr || D == nullptr)
+    return fail(DDM_ERR_INVALID_ARGUMENT, "frames_host/staging/D is NULL");
+  if (((uintptr_t)staging & 255) != 0) return fail(DDM_ERR_INVALID_ARGUMENT, "staging must be 256-byte aligned");
+  if (p->ws == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "no workspace attached (ddm_plan_set_workspace)");
+  if (p->f16) return fail(DDM_ERR_UNSUPPORTED, "host-resident frames take the FP32 spectrum store");
+  if (capturing(p)) return fail(DDM_ERR_UNSUPPORTED, "host-resident frames: not inside a graph capture");
+  const size_t fbytes = (size_t)p->W * p->H * (p->d.pixel == DDM_PIX_U8 ? 1 : 2);
+  const size_t slot0 = align256(fbytes);
+  if (staging_bytes < slot0 + 2 * fbytes)
+    return fail(DDM_ERR_OUT_OF_MEMORY, "staging %zu bytes < %zu (frame 0 and two frames)", staging_bytes,
+                slot0 + 2 * fbytes);
+  int fb;
+  int64_t gblocks;
+  partition(p, &fb, &gblocks);
+  const int per_half = (int)std::min<size_t>((size_t)fb, (staging_bytes - slot0) / 2 / fbytes);
+  const size_t half_bytes = align256((size_t)per_half * fbytes);
+  const int nf_batch = (slot0 + 2 * half_bytes <= staging_bytes) ? per_half : std::max(1, per_half - 1);
+  char* stage0 = (char*)staging;
+  char* half[2] = {stage0 + slot0, stage0 + slot0 + align256((size_t)nf_batch * fbytes)};
+  char* base = (char*)p->ws;
+  float2* inter = (float2*)base;
+  void* spec = base + align256((size_t)fb * p->frame_inter_bytes);
+  QTable qt{p->qoff_d, p->kxcnt_d};
+  const SlotMap sm{p->sbase_d, p->sN};
+  const char* host = (const char*)frames_host;
+  // the copies start once the plan's stream has reached this call (earlier
+  // calls may still read the staging memory)
+  hipError_t e = hipEventRecord(p->ev_start, p->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(p->s_copy, p->ev_start, 0);
+  if (e == hipSuccess) e = hipMemcpyAsync(stage0, host, fbytes, hipMemcpyHostToDevice, p->s_copy);
+  if (e != hipSuccess) return hip_fail(e, "frame 0 copy");
+  const int64_t gs = gblocks * kSpecQB;
+  int bi = 0;
+  for (int64_t s_lo = 0; s_lo < p->nslots; s_lo += gs) {
+    const int64_t s_hi = std::min(p->nslots, s_lo + gs);
+    for (int t0 = 0; t0 < p->N; t0 += nf_batch, ++bi) {
+      const int nf = std::min(nf_batch, p->N - t0);
+      const int k = bi % 2;
+      if (bi >= 2 && (e = hipStreamWaitEvent(p->s_copy, p->ev_used[k], 0)) != hipSuccess)
+        return hip_fail(e, "staging order");
+      e = hipMemcpyAsync(half[k], host + (size_t)t0 * fbytes, (size_t)nf * fbytes, hipMemcpyHostToDevice,
+                         p->s_copy);
+      if (e == hipSuccess) e = hipEventRecord(p->ev_h2d[k], p->s_copy);
+      if (e == hipSuccess) e = hipStreamWaitEvent(p->stream, p->ev_h2d[k], 0);
+      if (e != hipSuccess) return hip_fail(e, "frame batch copy");
+      {
+        ProfScope ps(p, DDM_KERNEL_ROW);
+        // the batch's frames are frames 0.. of the staging half; frame 0 of the stack is the reference
+        e = launch_row(p->stream, p->d.pixel, half[k], p->W, p->H, 0, nullptr, nf, p->d.precondition, inter, p->kxw,
+                       p->kxnyq > 0, p->twW, 1, stage0);
+      }
+      if (e == hipSuccess) e = hipEventRecord(p->ev_used[k], p->stream);
+      if (e != hipSuccess) return hip_fail(e, "row transform launch");
+      {
+        ProfScope ps(p, DDM_KERNEL_COL);
+        e = launch_col(p->stream, inter, p->H, p->kxw, p->ncol_tiles, t0, nf, p->N, qt, sm, s_lo, s_hi, kSpecQB,
+                       p->kxnyq, SpecOut{spec, nullptr, nullptr}, p->twH, 1);
+      }
+      if (e != hipSuccess) return hip_fail(e, "column transform launch");
+    }
+    {
+      ProfScope ps(p, DDM_KERNEL_TIME);
+      e = launch_time(p->stream, p->L, spec, kSpecQB, s_hi - s_lo, p->N, p->M, p->twT, p->ramp, p->qmap_d + s_lo,
+                      nullptr, D, p->tshape);
+    }
+    if (e != hipSuccess) return hip_fail(e, "time transform launch");
+  }
+  // the copy stream's last work (frame 0 only, for N = 1 batch) is ordered before
+  // the plan's stream continues
+  e = hipEventRecord(p->ev_start, p->s_copy);
+  if (e == hipSuccess) e = hipStreamWaitEvent(p->stream, p->ev_start, 0);
+  if (e != hipSuccess) return hip_fail(e, "copy join");
+  return DDM_OK;
 }
 
 ddm_status ddm_plan_status(ddm_plan_t p) {

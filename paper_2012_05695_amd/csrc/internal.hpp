@@ -70,9 +70,10 @@ enum : int32_t {
 // pack: slot 0 of every row carries R(0) + i R(W/2) (the Nyquist column is needed).
 // Frames t0 .. t0 + nframes - 1, or, when tsel (device, nframes entries) is not
 // NULL, frames tsel[0 .. nframes - 1]; intermediate frame z holds the z-th.
+// ref: frame 0 (subtracted when precondition); NULL means frames itself.
 hipError_t launch_row(hipStream_t s, int pixel, const void* frames, int W, int H, int64_t t0,
                       const int32_t* tsel, int nframes, int precondition, float2* inter, int kxw, int pack,
-                      const float2* tw, int tws);
+                      const float2* tw, int tws, const void* ref = nullptr);
 
 // Destination of the column transform: complex FP32, or complex FP16 scaled
 // by 2^qexp[q] when qexp is non-null (saturations counted in *sat).

@@ -62,10 +62,11 @@ __device__ __forceinline__ uint2 nt_load(const uint2* p) {
   return make_uint2(x[0], x[1]);
 }
 
+// ref0: frame 0 (subtracted when precondition).
 template <int W, int E, typename PIX, bool NT = false>
-__device__ __forceinline__ void row_item(const PIX* __restrict__ frames, int H, int t, int ybase, int nt,
-                                         int precondition, float2* __restrict__ out, int kxw, int pack,
-                                         const float2* __restrict__ tw, int tws, float2* lds_row, int tx) {
+__device__ __forceinline__ void row_item(const PIX* __restrict__ frames, const PIX* __restrict__ ref0, int H, int t,
+                                         int ybase, int nt, int precondition, float2* __restrict__ out, int kxw,
+                                         int pack, const float2* __restrict__ tw, int tws, float2* lds_row, int tx) {
   constexpr int T = W / E;
   constexpr bool WAVE = (T <= 64) && (64 % T == 0);  // a transform inside one wavefront
   constexpr int WL = lds_len<true>(W);
@@ -81,7 +82,7 @@ __device__ __forceinline__ void row_item(const PIX* __restrict__ frames, int H, 
   // padding group, so one contiguous 64-byte run).
   {
     const PIX* src = frames + ((size_t)t * H + ybase) * W;
-    const PIX* ref = frames + (size_t)ybase * W;
+    const PIX* ref = ref0 + (size_t)ybase * W;
     for (int g = tx; g < nt * CPR; g += nthr) {
       const int pp = g / CPR, n0 = (g % CPR) * 8;
       const int off = 2 * pp * W + n0;
@@ -137,7 +138,8 @@ __device__ __forceinline__ void row_item(const PIX* __restrict__ frames, int H, 
 }
 
 template <int W, int E, typename PIX>
-__global__ void __launch_bounds__(256) k_row(const PIX* __restrict__ frames, int H, int t0,
+__global__ void __launch_bounds__(256) k_row(const PIX* __restrict__ frames, const PIX* __restrict__ ref0, int H,
+                                             int t0,
                                              const int32_t* __restrict__ tsel, int precondition,
                                              float2* __restrict__ inter, int kxw, int pack,
                                              const float2* __restrict__ tw, int tws) {
@@ -146,7 +148,7 @@ __global__ void __launch_bounds__(256) k_row(const PIX* __restrict__ frames, int
   const int ybase = blockIdx.x * nt * 2;
   // frame t0 + z, or the z-th entry of the frame list
   const int t = (tsel != nullptr) ? tsel[blockIdx.y] : t0 + (int)blockIdx.y;
-  row_item<W, E, PIX>(frames, H, t, ybase, nt, precondition,
+  row_item<W, E, PIX>(frames, ref0, H, t, ybase, nt, precondition,
                       inter + ((size_t)blockIdx.y * H + ybase) * kxw, kxw, pack, tw, tws, lds_row, threadIdx.x);
 }
 
@@ -425,8 +427,8 @@ __global__ void __launch_bounds__(16 * (W / E)) k_step1(const PIX* __restrict__ 
       __syncthreads();
       if (s_val == 0) break;  // uniform: a wait ran out
       const int ybase = r * 2 * NTR;
-      row_item<W, E, PIX, true>(frames, H, f, ybase, NTR, precondition, buf + (size_t)ybase * kxw, kxw, pack, twW,
-                                1, lds, tx);
+      row_item<W, E, PIX, true>(frames, frames, H, f, ybase, NTR, precondition, buf + (size_t)ybase * kxw, kxw,
+                                pack, twW, 1, lds, tx);
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the rows have reached L2
       __syncthreads();
       if (threadIdx.x == 0) atomicAdd(&rows[k], 1);
@@ -514,21 +516,22 @@ ColCfg col_cfg(int H) {
 }
 
 template <int W, typename PIX>
-static hipError_t row_go(hipStream_t s, const void* frames, int H, int t0, const int32_t* tsel, int nframes,
-                         int pre, float2* inter, int kxw, int pack, const float2* tw, int tws) {
+static hipError_t row_go(hipStream_t s, const void* frames, const void* ref, int H, int t0, const int32_t* tsel,
+                         int nframes, int pre, float2* inter, int kxw, int pack, const float2* tw, int tws) {
   constexpr int E = (W % 3 == 0) ? 24 : 16;
   RowCfg c = row_cfg(W, H);
   dim3 grid(H / (2 * c.nt), nframes);
   hipLaunchKernelGGL((k_row<W, E, PIX>), grid, dim3(c.nt * c.T), c.lds, s,
-                     (const PIX*)frames, H, t0, tsel, pre, inter, kxw, pack, tw, tws);
+                     (const PIX*)frames, (const PIX*)ref, H, t0, tsel, pre, inter, kxw, pack, tw, tws);
   return hipGetLastError();
 }
 
 template <typename PIX>
-static hipError_t row_dispatch(hipStream_t s, const void* f, int W, int H, int t0, const int32_t* tsel, int nf,
-                               int pre, float2* inter, int kxw, int pack, const float2* tw, int tws) {
+static hipError_t row_dispatch(hipStream_t s, const void* f, const void* ref, int W, int H, int t0,
+                               const int32_t* tsel, int nf, int pre, float2* inter, int kxw, int pack,
+                               const float2* tw, int tws) {
   switch (W) {
-#define ROW_CASE(n) case n: return row_go<n, PIX>(s, f, H, t0, tsel, nf, pre, inter, kxw, pack, tw, tws);
+#define ROW_CASE(n) case n: return row_go<n, PIX>(s, f, ref, H, t0, tsel, nf, pre, inter, kxw, pack, tw, tws);
     ROW_CASE(16) ROW_CASE(32) ROW_CASE(64) ROW_CASE(128) ROW_CASE(256) ROW_CASE(512)
     ROW_CASE(1024) ROW_CASE(2048) ROW_CASE(4096)
     ROW_CASE(48) ROW_CASE(96) ROW_CASE(192) ROW_CASE(384) ROW_CASE(768) ROW_CASE(1536) ROW_CASE(3072)
@@ -540,11 +543,12 @@ static hipError_t row_dispatch(hipStream_t s, const void* f, int W, int H, int t
 
 hipError_t launch_row(hipStream_t s, int pixel, const void* frames, int W, int H, int64_t t0,
                       const int32_t* tsel, int nframes, int precondition, float2* inter, int kxw, int pack,
-                      const float2* tw, int tws) {
+                      const float2* tw, int tws, const void* ref) {
+  if (ref == nullptr) ref = frames;
   if (pixel == DDM_PIX_U8)
-    return row_dispatch<uint8_t>(s, frames, W, H, (int)t0, tsel, nframes, precondition, inter, kxw, pack, tw,
+    return row_dispatch<uint8_t>(s, frames, ref, W, H, (int)t0, tsel, nframes, precondition, inter, kxw, pack, tw,
                                  tws);
-  return row_dispatch<uint16_t>(s, frames, W, H, (int)t0, tsel, nframes, precondition, inter, kxw, pack, tw,
+  return row_dispatch<uint16_t>(s, frames, ref, W, H, (int)t0, tsel, nframes, precondition, inter, kxw, pack, tw,
                                 tws);
 }
 
