@@ -359,13 +359,15 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    # untimed profiling pass: which kernel dominates?
+    # untimed profiling pass over a few steps: which kernel dominates?
     kinds = ["row", "col", "step1", "time", "radial"]
     plan.set_profiling(kinds)
-    step()
+    nprof = 5
+    for _ in range(nprof):
+        step()
     torch.cuda.synchronize()
     prof = {k: plan.profile(k) for k in kinds}
-    prof = {k: v for k, v in prof.items() if v[1] > 0}  # kinds that launched
+    prof = {k: (v[0] / nprof, v[1] / nprof) for k, v in prof.items() if v[1] > 0}  # per step, kinds that launched
     dominant = max(prof, key=lambda k: prof[k][0])
     print("bench: per-kernel ms in one step: %s" % {k: round(v[0], 4) for k, v in prof.items()},
           file=sys.stderr, flush=True)

@@ -305,7 +305,7 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
   if (p->fused) {
     const int ipf = H / 32 + p->ncol_tiles;  // row items (32 rows each) + column items per frame
     p->s1_nwg = step1_workgroups(W);
-    p->s1_maxslots = N + p->s1_nwg / ipf + 4;
+    p->s1_maxslots = N + p->s1_nwg / ipf + 4 + step1_lag();
     const size_t ctl_bytes = step1_ctl_words(p->s1_maxslots) * sizeof(int32_t);
     p->s1_frames = 8 * step1_bufs() + (int)((ctl_bytes + p->frame_inter_bytes - 1) / p->frame_inter_bytes);
     p->fb_target = p->s1_frames;

@@ -110,6 +110,7 @@ hipError_t launch_col(hipStream_t s, const float2* inter, int H, int kxw, int nt
 // no work).
 bool step1_fusable(int W, int H, int ncol_tiles, int kxw);
 int step1_bufs();
+int step1_lag();  // steps between a slot's row items and its column items (DDM_STEP1_LAG overrides)
 int step1_workgroups(int W);
 __host__ __device__ size_t step1_ctl_words(int maxslots);
 hipError_t launch_step1(hipStream_t s, int pixel, const void* frames, int W, int N, int precondition,

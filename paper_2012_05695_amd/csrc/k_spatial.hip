@@ -284,13 +284,14 @@ __global__ void __launch_bounds__(CW * (H / E)) k_col(const float2* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Step one in one persistent launch, for square frames whose row intermediate
-// fits an XCD's L2 (W = H <= 512).  Each XCD runs its own ordered stream of
-// items: step s holds the NR row items of slot s (a frame claimed from a global
-// counter) and then the NC column items of slot s - 1, so that column items
-// find their rows done instead of waiting for them.  Row items write the frame's intermediate into one
-// of kStep1Bufs buffers of that XCD; column items read it back from the XCD's
-// L2 (loads that skip L1) and write the spectra store.  A workgroup takes the
+// Step one in one persistent launch, for square frames up to 512 x 512.  Each
+// XCD runs its own ordered stream of items: step s holds the NR row items of
+// slot s (a frame claimed from a global counter) and then the NC column items
+// of slot s - lag, so that column items find their rows done instead of
+// waiting for them.  Row items write the frame's intermediate into one of
+// nbufs buffers of that XCD (nbufs > lag); column items read it back (loads
+// that skip the CU's L1; from the XCD's L2 or the Infinity Cache) and write
+// the spectra store.  A workgroup takes the
 // next ticket of its XCD and waits only for items with lower tickets of the
 // same XCD (column items: the slot's rows; row items: the columns of the slot
 // that last used the buffer; a slot's frame claim: the previous slot's claim),
@@ -299,7 +300,11 @@ __global__ void __launch_bounds__(CW * (H / E)) k_col(const float2* __restrict__
 // host) instead of hanging.  Control words per XCD: ticket, then per slot the
 // claimed frame (kUnset until published), rows done and columns done.
 // ---------------------------------------------------------------------------
-constexpr int kStep1Bufs = 3;  // default frame buffers per XCD (at least 2: see below)
+// Default frame buffers per XCD and steps between a slot's rows and its
+// columns (512x512 x 1024 frames: 3 buffers and lag 1 0.92 ms, 4 and 2 0.83 ms,
+// 6 and 3 0.81 ms; 2 and 1 1.46 ms).  Buffers must exceed the lag.
+constexpr int kStep1Bufs = 6;
+constexpr int kStep1Lag = 3;
 constexpr int kUnset = -2;
 // bound of one wait, in ticks of the 100 MHz constant clock (0.2 s)
 constexpr uint64_t kWaitTicks = 20000000ull;
@@ -355,7 +360,7 @@ __global__ void __launch_bounds__(16 * (W / E)) k_step1(const PIX* __restrict__ 
                                                          const int32_t* __restrict__ qexp, int32_t* sat,
                                                          const float2* __restrict__ twW,
                                                          const float2* __restrict__ twH, int* __restrict__ ctl,
-                                                         int maxslots, int nbufs) {
+                                                         int maxslots, int nbufs, int lag) {
   constexpr int H = W;
   constexpr int T = W / E;
   constexpr int CW = 16;
@@ -399,7 +404,7 @@ __global__ void __launch_bounds__(16 * (W / E)) k_step1(const PIX* __restrict__ 
         atomicExch(&fidx[st], f);
       }
       const int fs = spin_value(&fidx[st], err);
-      const int fp = (st == 0) ? -1 : spin_value(&fidx[st - 1], err);
+      const int fp = (st < lag) ? -1 : spin_value(&fidx[st - lag], err);
       s_val = fs;
       s_val2 = fp;
     }
@@ -408,7 +413,7 @@ __global__ void __launch_bounds__(16 * (W / E)) k_step1(const PIX* __restrict__ 
     __syncthreads();
     if (fs < 0 && fp < 0) break;  // uniform: nothing left in this step or after it
     const bool is_row = r < NR;
-    const int k = is_row ? st : st - 1;  // the slot this item works on
+    const int k = is_row ? st : st - lag;  // the slot this item works on
     const int f = is_row ? fs : fp;
     if (f < 0) continue;  // uniform: this item's slot has no frame
     float2* buf = bufs + (size_t)(xcc * nbufs + k % nbufs) * frame_elems;
@@ -596,12 +601,20 @@ hipError_t launch_col(hipStream_t s, const float2* inter, int H, int kxw, int nt
 // ---- fused step one ----
 __host__ __device__ size_t step1_ctl_words(int maxslots) { return (size_t)8 * (1 + 3 * (size_t)maxslots) + 2; }
 
+int step1_lag() {
+  static const int env = [] {
+    const char* v = std::getenv("DDM_STEP1_LAG");
+    return v ? std::atoi(v) : 0;
+  }();
+  return (env >= 1 && env <= 4) ? env : kStep1Lag;
+}
+
 int step1_bufs() {
   static const int env = [] {
     const char* v = std::getenv("DDM_STEP1_BUFS");
     return v ? std::atoi(v) : 0;
   }();
-  return (env >= 2 && env <= 4) ? env : kStep1Bufs;
+  return (env >= 2 && env <= 8) ? env : kStep1Bufs;
 }
 
 bool step1_fusable(int W, int H, int ncol_tiles, int kxw) {
@@ -633,17 +646,18 @@ __global__ void k_copy_i32(const int32_t* __restrict__ src, int32_t* __restrict_
 template <int W, typename PIX>
 static hipError_t step1_go(hipStream_t s, const void* frames, int N, int pre, float2* bufs, int kxw, int ntiles,
                            int pack, int kxnyq, QTable qt, SlotMap sm, int s_lo, int s_hi, SpecOut out,
-                           const float2* twW, const float2* twH, int* ctl, int maxslots, int nwg, int nbufs) {
+                           const float2* twW, const float2* twH, int* ctl, int maxslots, int nwg, int nbufs,
+                           int lag) {
   constexpr int E = 16, T = W / E, CW = 16;
   const size_t lds = std::max((size_t)CW * lds_len<true>(W) * sizeof(float2), (size_t)CW * W * sizeof(float2));
   if (out.qexp != nullptr)
     hipLaunchKernelGGL((k_step1<W, E, PIX, true>), dim3(nwg), dim3(CW * T), lds, s, (const PIX*)frames, N, pre,
                        bufs, kxw, ntiles, pack, kxnyq, qt.qoff, qt.kxcnt, sm.sbase, sm.sN, s_lo, s_hi, out.spec,
-                       out.qexp, out.sat, twW, twH, ctl, maxslots, nbufs);
+                       out.qexp, out.sat, twW, twH, ctl, maxslots, nbufs, lag);
   else
     hipLaunchKernelGGL((k_step1<W, E, PIX, false>), dim3(nwg), dim3(CW * T), lds, s, (const PIX*)frames, N, pre,
                        bufs, kxw, ntiles, pack, kxnyq, qt.qoff, qt.kxcnt, sm.sbase, sm.sN, s_lo, s_hi, out.spec,
-                       nullptr, nullptr, twW, twH, ctl, maxslots, nbufs);
+                       nullptr, nullptr, twW, twH, ctl, maxslots, nbufs, lag);
   return hipGetLastError();
 }
 
@@ -657,7 +671,10 @@ hipError_t launch_step1(hipStream_t s, int pixel, const void* frames, int W, int
                         float2* bufs, int kxw, int ntiles, int kxnyq, QTable qt, SlotMap sm, int64_t s_lo,
                         int64_t s_hi, SpecOut out, const float2* twW, const float2* twH, int* ctl, int maxslots,
                         int nwg, int nbufs, int err_init) {
-  if (nbufs < 2) return hipErrorInvalidValue;  // a row item would wait on a later ticket
+  const int lag = step1_lag();
+  // a row item waits for the columns of slot k - nbufs, which are in step
+  // k - nbufs + lag: that must be an earlier step
+  if (nbufs <= lag) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_step1_init, dim3(64), dim3(256), 0, s, ctl, maxslots, err_init);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -666,9 +683,9 @@ hipError_t launch_step1(hipStream_t s, int pixel, const void* frames, int W, int
   case n:                                                                                                       \
     return pixel == DDM_PIX_U8                                                                                  \
                ? step1_go<n, uint8_t>(s, frames, N, precondition, bufs, kxw, ntiles, pack, kxnyq, qt, sm, lo,  \
-                                      hi, out, twW, twH, ctl, maxslots, nwg, nbufs)                             \
+                                      hi, out, twW, twH, ctl, maxslots, nwg, nbufs, lag)                        \
                : step1_go<n, uint16_t>(s, frames, N, precondition, bufs, kxw, ntiles, pack, kxnyq, qt, sm, lo, \
-                                       hi, out, twW, twH, ctl, maxslots, nwg, nbufs);
+                                       hi, out, twW, twH, ctl, maxslots, nwg, nbufs, lag);
   switch (W) {
     S1_CASE(64) S1_CASE(128) S1_CASE(256) S1_CASE(512)
     default:
