@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-stacks leg (graph launch vs a loop of single plans)")
     ap.add_argument("--batched-stacks", type=int, default=64)
+    ap.add_argument("--no-direct", action="store_true",
+                    help="skip the direct-difference leg (step two by Eq. (1) against the time transform)")
     ap.add_argument("--learned-curves", type=int, default=1_000_000)
     ap.add_argument("--learned-epochs", type=int, default=30)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -472,6 +474,10 @@ def main():
     plan16.status()
     plan16.close()
     out["host_frames"] = host_frames_leg(plan, frames, D, args.steps)
+    if not args.no_direct:
+        print("bench: direct-difference leg (max_lag and N sweeps against the time transform)", file=sys.stderr,
+              flush=True)
+        out["direct"] = direct_leg(frames, recipe["pixel"])
     del frames, D
     plan.close()
     torch.cuda.empty_cache()
@@ -508,6 +514,56 @@ def host_frames_leg(plan, frames, D, steps):
     return {"ms_per_stack": t_h, "frames_per_s": N / (t_h * 1e-3), "h2d_copy_ms": t_c,
             "h2d_GBs": pinned.numel() * pinned.element_size() / (t_c * 1e-3) / 1e9,
             "work": "structure function only (no bins), frames in pinned host memory, 2 x 64-frame staging"}
+
+
+def direct_leg(frames, pixel, reps=3):
+    """Step two by direct differences (method "direct") against the time
+    transform on the bench frames: a max_lag sweep at N = 1024 and an all-lags
+    sweep over N (the first N frames), step-two device ms per call from the
+    plan's event pairs; the direct kernel against the vector-ALU roof (four
+    vector instructions per difference pair: two subtractions, two FMAs) and,
+    where few lags make it memory-bound, against HBM (the spectra read once, D
+    written once)."""
+    import torch
+    from paper_2012_05695_amd import api
+    N, H, W = frames.shape
+    lane_ops = 256 * 4 * 16 * 2.4e9  # vector lane-instructions per second
+
+    def step_two_ms(n, M, method, fr):
+        p = api.Plan(W, H, n, pixel=pixel, max_lag=M, method=method)
+        p.allocate_workspace()
+        D = p.structure_function(fr)
+        p.set_profiling(["time"])
+        for _ in range(reps):
+            p.structure_function(fr, out=D)
+        torch.cuda.synchronize()
+        ms, k = p.profile("time")
+        p.status()
+        nq = p.n_q
+        p.close()
+        return ms / k, nq
+
+    lags = []
+    for M in (8, 16, 32, 48, 64, 128, 1024):
+        md, nq = step_two_ms(N, M, "direct", frames)
+        mf, _ = step_two_ms(N, M, "fourier", frames)
+        pairs = nq * (N * M - M * (M - 1) // 2)
+        byts = nq * (N * 8 + M * 4)
+        auto = api.Plan(W, H, N, pixel=pixel, max_lag=M, method="auto")
+        lags.append({"max_lag": M, "direct_ms": md, "fourier_ms": mf, "direct_over_fourier": md / mf,
+                     "direct_valu_frac": 4.0 * pairs / (md * 1e-3) / lane_ops,
+                     "direct_hbm_frac": byts / (md * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "auto_model_choice": auto.method})
+        auto.close()
+    sweep = []
+    for n in (16, 32, 64, 128, 256, 512, 1024):
+        fr = frames[:n].contiguous() if n < N else frames
+        md, _ = step_two_ms(n, n, "direct", fr)
+        mf, _ = step_two_ms(n, n, "fourier", fr)
+        sweep.append({"n_frames": n, "direct_ms": md, "fourier_ms": mf, "direct_over_fourier": md / mf})
+    torch.cuda.empty_cache()
+    return {"workload": "%dx%d frames of the bench stack, FP32 spectra store; step two only" % (W, H),
+            "max_lag_sweep_at_N%d" % N: lags, "all_lags_sweep": sweep}
 
 
 def finish(args, out, frames_cpu, nq):

@@ -74,13 +74,30 @@ typedef enum ddm_spectrum { DDM_SPEC_F32 = 0, DDM_SPEC_F16_QSCALED = 1 } ddm_spe
  * round trips per point, and are faster than POW2 only where N = L. */
 typedef enum ddm_padding { DDM_PAD_POW2 = 0, DDM_PAD_MINIMAL = 1 } ddm_padding;
 
+/* How step two computes D from the image spectra.
+ * FOURIER: the time transform of Appendix B (Eq. (B3), (B4)): O(N log N) per
+ *   wave vector, whatever max_lag is.
+ * DIRECT: Eq. (1) term by term, |F_{n+m}(q) - F_n(q)|^2 averaged over the
+ *   N - m pairs of each lag (the direct scheme of section "The algorithm",
+ *   applied to the stored spectra: the spectrum of a difference image is the
+ *   difference of the spectra): O(N M) per wave vector.  FP32 differences,
+ *   FP32 sums over 64 time points added into FP64 totals.  Cheaper than
+ *   FOURIER when few lags are wanted (at N = 1024 below about 40); the only
+ *   method for N above 8192 (up to 65536).
+ * AUTO: DIRECT where a cost model (N M - M (M - 1) / 2 pairs at four vector
+ *   operations each, against 16 L log2 L for the transform of length L)
+ *   expects it to be faster, else FOURIER; ddm_plan_autotune replaces the
+ *   model's choice by a timing of both.  ddm_plan_method reports the choice. */
+typedef enum ddm_method { DDM_METHOD_FOURIER = 0, DDM_METHOD_DIRECT = 1, DDM_METHOD_AUTO = 2 } ddm_method;
+
 typedef struct ddm_plan_s* ddm_plan_t;
 
 typedef struct ddm_plan_desc {
   uint32_t struct_size;  /* = sizeof(ddm_plan_desc); guards ABI drift */
   int32_t width;         /* W: even, 8..4096, a power of two or 3 * a power of two */
   int32_t height;        /* H: same rules as W */
-  int32_t n_frames;      /* N >= 2 (up to 8192: time FFT length N2 <= 16384) */
+  int32_t n_frames;      /* N >= 2 (up to 8192: time FFT length N2 <= 16384; up to
+                            65536 with DDM_METHOD_DIRECT) */
   int32_t max_lag;       /* M in [1, N]: lags 0..M-1 are produced; 0 means N */
   int32_t pixel;         /* ddm_pixel of the frames */
   int32_t spectrum;      /* ddm_spectrum */
@@ -88,13 +105,15 @@ typedef struct ddm_plan_desc {
                             because D depends on frame differences only; it
                             shrinks the dynamic range of the FP32 transforms) */
   int32_t padding;       /* ddm_padding of the time transform (default POW2) */
+  int32_t method;        /* ddm_method of step two (default FOURIER) */
   int64_t k2_max;        /* keep q with k2 <= k2_max (the paper's low-frequency
                             restriction, section "Conclusion"); -1 keeps all */
   void* stream;          /* hipStream_t for all work of this plan; NULL = default */
 } ddm_plan_desc;
 
 /* Fill a descriptor with defaults: struct_size set, max_lag 0, U16, F32,
- * precondition 1, k2_max -1, stream NULL.  Size fields are set to 0. */
+ * precondition 1, padding POW2, method FOURIER, k2_max -1, stream NULL.  Size
+ * fields are set to 0. */
 void ddm_plan_desc_init(ddm_plan_desc* desc);
 
 /* Create a plan.  Allocates only small device tables (twiddles, row offsets;
@@ -206,8 +225,16 @@ ddm_status ddm_structure_from_spectra(ddm_plan_t plan, const float* spectra_dev,
  * the plan's workspace (required); the choice is cached per (time length, N,
  * max_lag, storage) for the process and used by later calls.  Synchronises
  * the stream.  DDM_AUTOTUNE=off (environment) keeps the built-in shape.
- * Outputs (may be NULL): E, wave vectors per workgroup, estimated ms per call. */
+ * Outputs (may be NULL): E, wave vectors per workgroup, estimated ms per call
+ * of step two.  DDM_METHOD_AUTO plans also time the direct kernel on the same
+ * spectra and keep the faster method (the ms is that method's); DDM_METHOD_DIRECT
+ * plans time only the direct kernel. */
 ddm_status ddm_plan_autotune(ddm_plan_t plan, int32_t* E, int32_t* qpw, double* ms);
+
+/* The method step two uses (DDM_METHOD_FOURIER or DDM_METHOD_DIRECT): the
+ * descriptor's, or for DDM_METHOD_AUTO the cost model's choice, replaced by
+ * ddm_plan_autotune's timing once that has run. */
+ddm_status ddm_plan_method(ddm_plan_t plan, int32_t* method);
 
 /* ---------------------------------------------------------------------------
  * Batches of independent stacks of uneven sizes (many regions of interest or

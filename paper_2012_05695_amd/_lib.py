@@ -40,6 +40,9 @@ DDM_SPEC_F32 = 0
 DDM_SPEC_F16_QSCALED = 1
 DDM_PAD_POW2 = 0
 DDM_PAD_MINIMAL = 1
+DDM_METHOD_FOURIER = 0
+DDM_METHOD_DIRECT = 1
+DDM_METHOD_AUTO = 2
 
 STATUS_NAMES = {
     0: "DDM_OK",
@@ -63,6 +66,7 @@ class PlanDesc(ctypes.Structure):
         ("spectrum", c_int32),
         ("precondition", c_int32),
         ("padding", c_int32),
+        ("method", c_int32),
         ("k2_max", c_int64),
         ("stream", c_void_p),
     ]
@@ -107,6 +111,7 @@ SIGNATURES = [
      [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     ("ddm_plan_fp16_saturations", c_int32, [c_void_p, P(c_int64)]),
     ("ddm_plan_status", c_int32, [c_void_p]),
+    ("ddm_plan_method", c_int32, [c_void_p, P(c_int32)]),
     ("ddm_plan_set_profiling", c_int32, [c_void_p, c_uint32]),
     ("ddm_plan_get_profile", c_int32, [c_void_p, c_uint32, P(ctypes.c_double), P(c_int64)]),
     ("ddm_sample_curves", c_int32,

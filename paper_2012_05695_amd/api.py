@@ -44,6 +44,8 @@ _PIX = {"u8": L.DDM_PIX_U8, "u16": L.DDM_PIX_U16}
 _PIX_DTYPES = {L.DDM_PIX_U8: (torch.uint8,), L.DDM_PIX_U16: (torch.uint16, torch.int16)}
 _SPEC = {"f32": L.DDM_SPEC_F32, "f16": L.DDM_SPEC_F16_QSCALED}
 _PAD = {"pow2": L.DDM_PAD_POW2, "minimal": L.DDM_PAD_MINIMAL}
+_METHOD = {"fourier": L.DDM_METHOD_FOURIER, "direct": L.DDM_METHOD_DIRECT, "auto": L.DDM_METHOD_AUTO}
+_METHOD_NAME = {v: k for k, v in _METHOD.items()}
 
 
 def _stream_handle(stream):
@@ -74,7 +76,7 @@ class Plan:
     """
 
     def __init__(self, width, height, n_frames, max_lag=0, pixel="u16", spectrum="f32",
-                 precondition=True, k2_max=-1, padding="pow2", stream=None, device=None):
+                 precondition=True, k2_max=-1, padding="pow2", method="fourier", stream=None, device=None):
         if device is None:
             device = torch.cuda.current_device()
         self.device = int(device)
@@ -90,6 +92,7 @@ class Plan:
         d.precondition = 1 if precondition else 0
         d.k2_max = int(k2_max)
         d.padding = _PAD[padding] if isinstance(padding, str) else int(padding)
+        d.method = _METHOD[method] if isinstance(method, str) else int(method)
         with torch.cuda.device(self.device):
             d.stream = _stream_handle(stream).value
         self._desc = d
@@ -134,6 +137,13 @@ class Plan:
         _check(_lib.ddm_plan_q_index(self._h, kx.ctypes.data, ky.ctypes.data))
         return kx, ky
 
+    @property
+    def method(self):
+        """Step two's method: "fourier" or "direct" (ddm_plan_method)."""
+        m = ctypes.c_int32()
+        _check(_lib.ddm_plan_method(self._h, ctypes.byref(m)))
+        return _METHOD_NAME[int(m.value)]
+
     def workspace_size(self):
         mn, full = ctypes.c_size_t(), ctypes.c_size_t()
         _check(_lib.ddm_plan_workspace_size(self._h, ctypes.byref(mn), ctypes.byref(full)))
@@ -152,7 +162,9 @@ class Plan:
         return ws
 
     def autotune(self):
-        """Time the time-kernel launch shapes on this plan's workspace; returns (E, qpw, ms)."""
+        """Time the time-kernel launch shapes (and, for method "auto", the direct
+        kernel, keeping the faster method) on this plan's workspace; returns
+        (E, qpw, ms of step two per call)."""
         if self._ws is None:
             self.allocate_workspace()
         E, q, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
@@ -454,7 +466,7 @@ class Batch:
     """Independent stacks of uneven sizes in one graph launch (ddm_batch_* of include/ddm.h).
 
     shapes: list of (W, H, N) or dicts with Plan keyword fields (width, height,
-    n_frames, max_lag, pixel, precondition, k2_max, padding)."""
+    n_frames, max_lag, pixel, precondition, k2_max, padding, method)."""
 
     def __init__(self, shapes, lanes=4, padding="pow2", stream=None, device=None):
         if device is None:
@@ -475,6 +487,8 @@ class Batch:
             d.k2_max = int(sh.get("k2_max", -1))
             pad = sh.get("padding", padding)
             d.padding = _PAD[pad] if isinstance(pad, str) else int(pad)
+            meth = sh.get("method", "fourier")
+            d.method = _METHOD[meth] if isinstance(meth, str) else int(meth)
             self.shapes.append(sh)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):

@@ -60,6 +60,16 @@ namespace {
 constexpr size_t kInterTargetBytes = 128u << 20;  // row-transform intermediate per batch (half the Infinity Cache)
 constexpr int kReadback = 4;                      // calls in flight before the host waits
 
+// Step two's cost model: the direct method evaluates N M - M (M - 1) / 2
+// difference pairs per wave vector at four vector operations each; the time
+// transform of length L costs about 16 L log2 L operations per wave vector
+// (three L-point transforms with their pre- and post-processing).
+bool direct_cheaper(int N, int M, int L) {
+  const double pairs = (double)N * M - 0.5 * (double)M * (M - 1);
+  const double fourier = 16.0 * L * std::log2((double)L);
+  return 4.0 * pairs < fourier;
+}
+
 }  // namespace
 
 struct ddm_plan_s {
@@ -67,6 +77,7 @@ struct ddm_plan_s {
   ddm_plan_desc d;
   int W, H, N, M;
   int L;         // time transform length (N2 / 2), >= 16
+  int method;    // step two: DDM_METHOD_FOURIER or DDM_METHOD_DIRECT (AUTO resolved)
   int n2_paper;  // Eq. (B4) length
   int64_t nq;
   int64_t ca, cc;  // k2 = kx^2 ca + ky_s^2 cc
@@ -235,7 +246,11 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
     return fail(DDM_ERR_UNSUPPORTED,
                 "frame %dx%d: each side must be 2^k (16..4096) or 3*2^k (48..3072)", W, H);
   if (N < 2) return fail(DDM_ERR_INVALID_ARGUMENT, "n_frames must be >= 2");
-  if (N > 8192) return fail(DDM_ERR_UNSUPPORTED, "n_frames > 8192 (time FFT length > 16384)");
+  if (desc->method != DDM_METHOD_FOURIER && desc->method != DDM_METHOD_DIRECT && desc->method != DDM_METHOD_AUTO)
+    return fail(DDM_ERR_INVALID_ARGUMENT, "method must be DDM_METHOD_FOURIER, _DIRECT or _AUTO");
+  if (N > 65536) return fail(DDM_ERR_UNSUPPORTED, "n_frames > 65536");
+  if (N > 8192 && desc->method == DDM_METHOD_FOURIER)
+    return fail(DDM_ERR_UNSUPPORTED, "n_frames > 8192 (time FFT length > 16384) needs DDM_METHOD_DIRECT");
   if (desc->max_lag < 0 || desc->max_lag > N)
     return fail(DDM_ERR_INVALID_ARGUMENT, "max_lag must be in [0, n_frames]");
   if (desc->pixel != DDM_PIX_U8 && desc->pixel != DDM_PIX_U16)
@@ -260,6 +275,9 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
   while (l < N) l <<= 1;
   p->n2_paper = 2 * l;
   p->L = time_length(N, desc->padding);
+  p->method = desc->method == DDM_METHOD_AUTO ? (N > 8192 || direct_cheaper(N, p->M, p->L) ? DDM_METHOD_DIRECT
+                                                                                         : DDM_METHOD_FOURIER)
+                                              : desc->method;
   const int64_t g = std::gcd(W, H);
   p->ca = (int64_t)(H / g) * (H / g);
   p->cc = (int64_t)(W / g) * (W / g);
@@ -471,6 +489,14 @@ ddm_status ddm_plan_destroy(ddm_plan_t p) {
   return DDM_OK;
 }
 
+ddm_status ddm_plan_method(ddm_plan_t p, int32_t* method) {
+  ddm_status st = check_plan(p);
+  if (st != DDM_OK) return st;
+  if (method == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "method is NULL");
+  *method = p->method;
+  return DDM_OK;
+}
+
 ddm_status ddm_plan_query(ddm_plan_t p, int64_t* n_q, int32_t* max_lag, int32_t* n2) {
   ddm_status st = check_plan(p);
   if (st != DDM_OK) return st;
@@ -529,6 +555,14 @@ ddm_status ddm_plan_set_workspace(ddm_plan_t p, void* ws, size_t bytes) {
 
 // Split the workspace (after the FP16 auxiliaries) into the row intermediate
 // (fb frames) and the spectra store of one group (gblocks q-blocks).
+// Step two over slots [0, nslots) of a spectra store (layout qb: 16 blocked,
+// 1 plain) with the plan's method.
+static hipError_t launch_step_two(ddm_plan_s* p, const void* spec, int qb, int64_t nslots, const int32_t* qmap,
+                                  const int32_t* qexp, float* D) {
+  if (p->method == DDM_METHOD_DIRECT) return launch_direct(p->stream, spec, qb, nslots, p->N, p->M, qmap, qexp, D);
+  return launch_time(p->stream, p->L, spec, qb, nslots, p->N, p->M, p->twT, p->ramp, qmap, qexp, D, p->tshape);
+}
+
 static void partition(const ddm_plan_s* p, int* fb, int64_t* gblocks) {
   const size_t blk = spec_block_bytes(p);
   const int64_t nb = n_spec_blocks(p);
@@ -712,8 +746,7 @@ static ddm_status structure_function_run(ddm_plan_s* p, const void* frames, floa
     if (st != DDM_OK) return st;
     {
       ProfScope ps(p, DDM_KERNEL_TIME);
-      e = launch_time(p->stream, p->L, spec, kSpecQB, s_hi - s_lo, p->N, p->M, p->twT, p->ramp, p->qmap_d + s_lo,
-                      qexp, D, p->tshape);
+      e = launch_step_two(p, spec, kSpecQB, s_hi - s_lo, p->qmap_d + s_lo, qexp, D);
     }
     if (e != hipSuccess) return hip_fail(e, "time transform launch");
   }
@@ -876,8 +909,7 @@ ddm_status ddm_structure_function_host(ddm_plan_t p, const void* frames_host, vo
     }
     {
       ProfScope ps(p, DDM_KERNEL_TIME);
-      e = launch_time(p->stream, p->L, spec, kSpecQB, s_hi - s_lo, p->N, p->M, p->twT, p->ramp, p->qmap_d + s_lo,
-                      nullptr, D, p->tshape);
+      e = launch_step_two(p, spec, kSpecQB, s_hi - s_lo, p->qmap_d + s_lo, nullptr, D);
     }
     if (e != hipSuccess) return hip_fail(e, "time transform launch");
   }
@@ -940,7 +972,7 @@ ddm_status ddm_structure_from_spectra(ddm_plan_t p, const float* spectra, float*
   hipError_t e;
   {
     ProfScope ps(p, DDM_KERNEL_TIME);
-    e = launch_time(p->stream, p->L, spectra, 1, p->nq, p->N, p->M, p->twT, p->ramp, nullptr, nullptr, D, p->tshape);
+    e = launch_step_two(p, spectra, 1, p->nq, nullptr, nullptr, D);
   }
   if (e != hipSuccess) return hip_fail(e, "time transform launch");
   return DDM_OK;
@@ -1120,32 +1152,43 @@ ddm_status ddm_fit(const ddm_fit_desc* f, const float* curves, const float* lags
 // ---------------------------------------------------------------------------
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int, int>, std::tuple<int, int, double>> g_tune;
+static std::map<std::tuple<int, int, int, int>, double> g_tune_direct;  // direct-method ms
 
 ddm_status ddm_plan_autotune(ddm_plan_t p, int32_t* E_out, int32_t* qpw_out, double* ms_out) {
   ddm_status st = check_plan(p);
   if (st != DDM_OK) return st;
   if (p->ws == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "autotune needs the workspace (ddm_plan_set_workspace)");
   const char* env = std::getenv("DDM_AUTOTUNE");
+  const bool off = env && std::strcmp(env, "off") == 0;
+  const bool want_fourier = p->d.method != DDM_METHOD_DIRECT && p->N <= 8192;
+  const bool want_direct = p->d.method != DDM_METHOD_FOURIER;
   const auto key = std::make_tuple(p->L, p->N, p->M, (int)p->f16);
-  double best_ms = -1.0;
-  TimeShape best{};
-  bool have = false;
+  double best_ms = -1.0, direct_ms = -1.0;
+  TimeShape best = p->tshape;
+  bool have = !want_fourier, have_d = !want_direct;
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune.find(key);
-    if (it != g_tune.end()) {
+    if (want_fourier && it != g_tune.end()) {
       best.E = std::get<0>(it->second);
       best.qpw = std::get<1>(it->second);
       best_ms = std::get<2>(it->second);
       have = true;
     }
+    auto id = g_tune_direct.find(key);
+    if (want_direct && id != g_tune_direct.end()) {
+      direct_ms = id->second;
+      have_d = true;
+    }
   }
-  if (!have && !(env && std::strcmp(env, "off") == 0)) {
+  if ((!have || !have_d) && !off) {
+    // zero-filled spectra of nq_t slots in the workspace, D into the
+    // row-intermediate region
     int fb;
     int64_t gblocks;
     partition(p, &fb, &gblocks);
     char* base = (char*)p->ws + aux_bytes(p);
-    float* dout = (float*)base;                       // row-intermediate region as D scratch
+    float* dout = (float*)base;
     void* spec = base + align256((size_t)fb * p->frame_inter_bytes);
     int64_t nq_t = std::min<int64_t>(gblocks * kSpecQB, 65536);
     nq_t = std::min<int64_t>(nq_t, (int64_t)(((size_t)fb * p->frame_inter_bytes) / ((size_t)p->M * 4)));
@@ -1161,39 +1204,54 @@ ddm_status ddm_plan_autotune(ddm_plan_t p, int32_t* E_out, int32_t* qpw_out, dou
     hipEvent_t a = nullptr, b = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
-    for (int E : {16, 8, 12}) {
-      for (int qpw : {1, 2, 4, 8, 16}) {
-        if (e != hipSuccess) break;
-        // 2^k lengths take E = 16 or 8 (8 from L = 512 on); 3 * 2^k lengths E = 12
-        if ((p->L % 3 == 0) != (E == 12)) continue;
-        if (p->L / E < 1 || p->L % E != 0 || (E == 8 && p->L < 512)) continue;
-        if (qpw * (p->L / E) > 1024 || time_lds_bytes(p->L, qpw) > 160 * 1024) continue;
-        const TimeShape sh{E, qpw};
-        e = launch_time(p->stream, p->L, spec, kSpecQB, nq_t, p->N, p->M, p->twT, p->ramp, nullptr, qexp, dout, sh);
-        if (e == hipSuccess) e = hipEventRecord(a, p->stream);
-        for (int r = 0; r < 2 && e == hipSuccess; ++r)
-          e = launch_time(p->stream, p->L, spec, kSpecQB, nq_t, p->N, p->M, p->twT, p->ramp, nullptr, qexp, dout, sh);
-        if (e == hipSuccess) e = hipEventRecord(b, p->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(b);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-        if (e == hipSuccess && (best_ms < 0 || ms < best_ms)) {
-          best_ms = ms;
-          best = sh;
+    // one untimed launch, then two timed: ms per launch over all slots
+    auto time_it = [&](auto&& launch, double* ms_all) {
+      e = launch();
+      if (e == hipSuccess) e = hipEventRecord(a, p->stream);
+      for (int r = 0; r < 2 && e == hipSuccess; ++r) e = launch();
+      if (e == hipSuccess) e = hipEventRecord(b, p->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+      *ms_all = ms / 2.0 * ((double)p->nslots / (double)nq_t);
+    };
+    if (!have) {
+      for (int E : {16, 8, 12}) {
+        for (int qpw : {1, 2, 4, 8, 16}) {
+          if (e != hipSuccess) break;
+          // 2^k lengths take E = 16 or 8 (8 from L = 512 on); 3 * 2^k lengths E = 12
+          if ((p->L % 3 == 0) != (E == 12)) continue;
+          if (p->L / E < 1 || p->L % E != 0 || (E == 8 && p->L < 512)) continue;
+          if (qpw * (p->L / E) > 1024 || time_lds_bytes(p->L, qpw) > 160 * 1024) continue;
+          const TimeShape sh{E, qpw};
+          double ms = 0.0;
+          time_it([&] {
+            return launch_time(p->stream, p->L, spec, kSpecQB, nq_t, p->N, p->M, p->twT, p->ramp, nullptr, qexp, dout,
+                               sh);
+          }, &ms);
+          if (e == hipSuccess && (best_ms < 0 || ms < best_ms)) {
+            best_ms = ms;
+            best = sh;
+          }
         }
       }
     }
+    if (!have_d && e == hipSuccess)
+      time_it([&] { return launch_direct(p->stream, spec, kSpecQB, nq_t, p->N, p->M, nullptr, qexp, dout); },
+              &direct_ms);
     if (a) hipEventDestroy(a);
     if (b) hipEventDestroy(b);
     if (e != hipSuccess) return hip_fail(e, "autotune");
-    best_ms = best_ms / 2.0 * ((double)p->nslots / (double)nq_t);  // per launch over all slots
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune[key] = std::make_tuple(best.E, best.qpw, best_ms);
+    if (!have) g_tune[key] = std::make_tuple(best.E, best.qpw, best_ms);
+    if (!have_d) g_tune_direct[key] = direct_ms;
   }
   p->tshape = best;
+  if (p->d.method == DDM_METHOD_AUTO && best_ms > 0 && direct_ms > 0)
+    p->method = direct_ms < best_ms ? DDM_METHOD_DIRECT : DDM_METHOD_FOURIER;
   if (E_out) *E_out = best.E;
   if (qpw_out) *qpw_out = best.qpw;
-  if (ms_out) *ms_out = best_ms;
+  if (ms_out) *ms_out = p->method == DDM_METHOD_DIRECT ? direct_ms : best_ms;
   return DDM_OK;
 }
 

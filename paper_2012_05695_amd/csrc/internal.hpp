@@ -140,6 +140,12 @@ int time_length(int N, int minimal);
 
 // L: the plan's transform length (time_length(N) when the plan was made; twN2
 // holds 2 L entries).
+// Step two by direct differences (Eq. (1) term by term) over slots [0, nslots)
+// of a spectra store laid out as for launch_time (qb 16 blocked, 1 plain);
+// qexp: the blocked FP16 store's per-row exponents, else null.
+hipError_t launch_direct(hipStream_t s, const void* spec, int qb, int64_t nslots, int N, int M,
+                         const int32_t* qmap, const int32_t* qexp, float* D);
+
 hipError_t launch_time(hipStream_t s, int L, const void* spec, int qb, int64_t nslots_group, int N, int M,
                        const float2* twN2, const double* ramp, const int32_t* qmap,
                        const int32_t* qexp, float* D_rows,

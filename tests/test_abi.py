@@ -86,6 +86,19 @@ def test_host_only_calls(libddm_path):
     d.n_frames, d.max_lag = 8, 9
     assert lib.ddm_plan_create(ctypes.byref(d), ctypes.byref(h)) == _lib.DDM_ERR_INVALID_ARGUMENT
     assert lib.ddm_plan_create(None, ctypes.byref(h)) == _lib.DDM_ERR_INVALID_ARGUMENT
+    # step two's method: unknown values, and the lengths each method takes
+    lib.ddm_plan_desc_init(ctypes.byref(d))
+    assert d.method == _lib.DDM_METHOD_FOURIER and d.padding == _lib.DDM_PAD_POW2
+    d.width, d.height, d.n_frames = 64, 64, 8
+    d.method = 3
+    assert lib.ddm_plan_create(ctypes.byref(d), ctypes.byref(h)) == _lib.DDM_ERR_INVALID_ARGUMENT
+    assert b"method" in lib.ddm_last_error()
+    d.method, d.n_frames = _lib.DDM_METHOD_FOURIER, 8193
+    assert lib.ddm_plan_create(ctypes.byref(d), ctypes.byref(h)) == _lib.DDM_ERR_UNSUPPORTED
+    assert b"DDM_METHOD_DIRECT" in lib.ddm_last_error()
+    d.method, d.n_frames = _lib.DDM_METHOD_DIRECT, 65537
+    assert lib.ddm_plan_create(ctypes.byref(d), ctypes.byref(h)) == _lib.DDM_ERR_UNSUPPORTED
+    assert lib.ddm_plan_method(None, None) == _lib.DDM_ERR_INVALID_ARGUMENT
     assert lib.ddm_plan_destroy(None) == _lib.DDM_OK
     assert lib.ddm_structure_function(None, None, None) == _lib.DDM_ERR_INVALID_ARGUMENT
 
