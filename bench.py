@@ -14,6 +14,7 @@ plan's stream) and the CPU oracle timed on a bounded sample.
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -140,6 +141,90 @@ def cpu_baseline(frames_cpu, ncols, nq_total):
         pass
     return {"value": N / full_s, "unit": "frames/s", "cores": threads, "kind": "oracle", "sample": sample,
             "cpu": cpu, "host_cpus": os.cpu_count()}
+
+
+def cpu_fourier(frames, max_lag=0, workers=None, chunk=256):
+    """The paper's Fourier method on the host (its CPU WITH_FT mode; section
+    "The algorithm" and Appendix B), as a second host baseline beside the
+    O(N^2) oracle: pocketfft (scipy.fft) in single precision, like the device
+    path, on `workers` threads; not part of the library, which has no CPU path.
+
+    Step one: the 2-D real transform of every frame minus frame 0 (D depends on
+    differences only), batches of frames on all threads.  Step two: chunks of
+    `chunk` wave vectors, one chunk per thread at a time: the temporal mean
+    removed (D is unchanged), the zero-padded transform of length 2L >= 2N - 1
+    (Eq. (B4)), the inverse of its squared modulus (the autocorrelation; only
+    its real part is needed, the inverse of the even part of the squared
+    modulus, a half-length real transform), and Eq. (B3) with FP64 prefix sums
+    of |F_n|^2.  frames: array [N, H, W] (integers); returns D [H (W/2 + 1), M]
+    float64 in the library's q order (ky-major, then kx)."""
+    import numpy as np
+    import scipy.fft as sfft
+    from concurrent.futures import ThreadPoolExecutor
+    fr = np.asarray(frames)
+    N, H, W = fr.shape
+    M = N if not max_lag else int(max_lag)
+    if workers is None:
+        workers = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    f0 = fr[0].astype(np.float32)
+    F = np.empty((N, H, W // 2 + 1), dtype=np.complex64)
+    for t0 in range(0, N, 64):
+        F[t0:t0 + 64] = sfft.rfft2(fr[t0:t0 + 64].astype(np.float32) - f0, workers=workers)
+    Fq = F.reshape(N, -1).T                                   # [Q, N] (a strided view)
+    Q = Fq.shape[0]
+    L2 = 1
+    while L2 < 2 * N - 1:
+        L2 <<= 1
+    D = np.empty((Q, M), dtype=np.float64)
+    ramp = 1.0 / (N - np.arange(1, M, dtype=np.float64))
+    neg = (-np.arange(L2 // 2 + 1)) % L2
+    m = np.arange(1, M)
+
+    def run(q0):
+        x = np.ascontiguousarray(Fq[q0:q0 + chunk])
+        x -= x.mean(axis=1, keepdims=True)
+        X = sfft.fft(x, n=L2, axis=1)
+        P = X.real ** 2 + X.imag ** 2
+        s = sfft.irfft(0.5 * (P[:, :L2 // 2 + 1] + P[:, neg]), n=L2, axis=1)
+        c = np.zeros((x.shape[0], N + 1))
+        np.cumsum(x.real.astype(np.float64) ** 2 + x.imag.astype(np.float64) ** 2, axis=1, out=c[:, 1:])
+        # sum_{n<N-m} |F_n|^2 + sum_{n>=m} |F_n|^2 - 2 Re sum_n F_{n+m} F_n^*, over N - m
+        out = D[q0:q0 + chunk]
+        out[:, 0] = 0.0
+        out[:, 1:] = c[:, N - m] + (c[:, N:N + 1] - c[:, m]) - 2.0 * s[:, 1:M]
+        out[:, 1:] *= ramp
+
+    with ThreadPoolExecutor(workers) as ex:
+        list(ex.map(run, range(0, Q, chunk)))
+    return D
+
+
+def cpu_fourier_leg(frames_cpu, thresholds, nbins):
+    """The host Fourier method on the whole bench workload, binned: frames/s."""
+    import numpy as np
+    import scipy.sparse
+    workers = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    fr = frames_cpu.numpy()
+    N, H, W = fr.shape
+    t0 = time.perf_counter()
+    D = cpu_fourier(fr, workers=workers)
+    # bins as ddm_radial_average: T[b] <= k2 < T[b+1], k2 = kx^2 ca + ky^2 cc,
+    # weight 2 for 0 < kx < W/2 (the other half plane), weighted means
+    g = math.gcd(W, H)
+    ca, cc = (H // g) ** 2, (W // g) ** 2
+    ky = np.repeat(np.arange(H), W // 2 + 1)
+    kx = np.tile(np.arange(W // 2 + 1), H)
+    kys = np.where(ky <= H // 2, ky, ky - H).astype(np.int64)
+    k2 = kx.astype(np.int64) ** 2 * ca + kys ** 2 * cc
+    b = np.searchsorted(np.asarray(thresholds, dtype=np.int64), k2, side="right") - 1
+    w = np.where((kx > 0) & (kx < W // 2), 2.0, 1.0)
+    ok = np.nonzero((b >= 0) & (b < nbins))[0]
+    S = scipy.sparse.csr_matrix((w[ok], (b[ok], ok)), shape=(nbins, D.shape[0]))
+    cnt = np.asarray(S.sum(axis=1)).ravel()
+    Dbar = (S @ D) / np.maximum(cnt, 1.0)[:, None]
+    dt = time.perf_counter() - t0
+    return {"value": N / dt, "unit": "frames/s", "cores": workers, "kind": "host Fourier method (scipy.fft)",
+            "sample": "whole workload: all %d q, all %d lags, %d bins (%.2f s)" % (D.shape[0], N, nbins, dt)}
 
 
 def learned_leg(log):
@@ -474,6 +559,9 @@ def main():
     plan16.status()
     plan16.close()
     out["host_frames"] = host_frames_leg(plan, frames, D, args.steps)
+    if frames_cpu is not None:
+        print("bench: host Fourier method (scipy.fft) on the whole workload", file=sys.stderr, flush=True)
+        out["cpu_fourier"] = cpu_fourier_leg(frames_cpu, thr, nbins)
     if not args.no_direct:
         print("bench: direct-difference leg (max_lag and N sweeps against the time transform)", file=sys.stderr,
               flush=True)
