@@ -524,10 +524,12 @@ ddm_status ddm_plan_q_index(ddm_plan_t p, int32_t* kx_host, int32_t* ky_signed_h
 static size_t spec_elem_bytes(const ddm_plan_s* p) { return p->f16 ? 4 : sizeof(float2); }
 static size_t spec_block_bytes(const ddm_plan_s* p) { return (size_t)p->N * kSpecQB * spec_elem_bytes(p); }
 static int64_t n_spec_blocks(const ddm_plan_s* p) { return p->nslots / kSpecQB; }
-// FP16 store only: pilot spectra [nq][np], per-q exponents, saturation counter
+// FP16 store only: pilot spectra [nq][np], per-q exponents, saturation
+// counter, the exponents on the (ky, kx) grid [H][W/2 + 1] (int8)
 static size_t aux_bytes(const ddm_plan_s* p) {
   if (!p->f16) return 0;
-  return align256((size_t)p->nq * p->pilot.size() * sizeof(float2)) + align256((size_t)p->nq * 4) + 256;
+  return align256((size_t)p->nq * p->pilot.size() * sizeof(float2)) + align256((size_t)p->nq * 4) + 256 +
+         align256((size_t)p->H * (p->W / 2 + 1));
 }
 
 ddm_status ddm_plan_workspace_size(ddm_plan_t p, size_t* min_bytes, size_t* full_bytes) {
@@ -642,7 +644,7 @@ static ddm_status run_step_one(ddm_plan_s* p, const void* frames, float2* inter,
 // the intermediate holds, derive the per-q exponents, clear the saturation
 // counter.
 static ddm_status run_pilot(ddm_plan_s* p, const void* frames, float2* inter, int fb, float2* pilot,
-                            int32_t* qexp, int32_t* sat) {
+                            int32_t* qexp, int32_t* sat, int8_t* qgrid) {
   QTable qt{p->qoff_d, p->kxcnt_d};
   const int np = (int)p->pilot.size();
   for (int i0 = 0; i0 < np; i0 += fb) {
@@ -655,6 +657,7 @@ static ddm_status run_pilot(ddm_plan_s* p, const void* frames, float2* inter, in
     if (e != hipSuccess) return hip_fail(e, "pilot transform launch");
   }
   hipError_t e = launch_qexp(p->stream, pilot, np, p->nq, qexp);
+  if (e == hipSuccess) e = launch_qgrid(p->stream, qexp, qt, p->H, p->W / 2 + 1, qgrid);
   if (e == hipSuccess) e = launch_fill_i32(p->stream, sat, 1, 0);
   if (e != hipSuccess) return hip_fail(e, "FP16 scale launch");
   return DDM_OK;
@@ -727,22 +730,25 @@ static ddm_status structure_function_run(ddm_plan_s* p, const void* frames, floa
   char* base = (char*)p->ws;
   float2* pilot = nullptr;
   int32_t *qexp = nullptr, *sat = nullptr;
+  int8_t* qgrid = nullptr;
   if (p->f16) {
     pilot = (float2*)base;
     qexp = (int32_t*)(base + align256((size_t)p->nq * p->pilot.size() * sizeof(float2)));
     sat = (int32_t*)((char*)qexp + align256((size_t)p->nq * 4));
+    qgrid = (int8_t*)sat + 256;
     base += aux_bytes(p);
   }
   float2* inter = (float2*)base;
   void* spec = base + align256((size_t)fb * p->frame_inter_bytes);
   if (p->f16) {
-    st = run_pilot(p, frames, inter, fb, pilot, qexp, sat);
+    st = run_pilot(p, frames, inter, fb, pilot, qexp, sat, qgrid);
     if (st != DDM_OK) return st;
   }
   const int64_t gs = gblocks * kSpecQB;
   for (int64_t s_lo = 0; s_lo < p->nslots; s_lo += gs) {
     const int64_t s_hi = std::min(p->nslots, s_lo + gs);
-    st = run_step_one(p, frames, inter, fb, s_lo, s_hi, kSpecQB, SpecOut{spec, qexp, sat}, s_lo == 0);
+    st = run_step_one(p, frames, inter, fb, s_lo, s_hi, kSpecQB, SpecOut{spec, qgrid, sat, p->W / 2 + 1},
+                      s_lo == 0);
     if (st != DDM_OK) return st;
     {
       ProfScope ps(p, DDM_KERNEL_TIME);

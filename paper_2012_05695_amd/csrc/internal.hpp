@@ -76,11 +76,13 @@ hipError_t launch_row(hipStream_t s, int pixel, const void* frames, int W, int H
                       const float2* tw, int tws, const void* ref = nullptr);
 
 // Destination of the column transform: complex FP32, or complex FP16 scaled
-// by 2^qexp[q] when qexp is non-null (saturations counted in *sat).
+// by 2^qexp[q] when qgrid (the same exponents on the (ky, kx) grid) is
+// non-null (saturations counted in *sat).
 struct SpecOut {
   void* spec;
-  const int32_t* qexp;
-  int32_t* sat;
+  const int8_t* qgrid;  // FP16 store: exponents on the (ky, kx) grid, row stride qgw = W/2 + 1; null for FP32
+  int32_t* sat;         // FP16 store: saturation counter
+  int qgw;
 };
 
 // Slot of each kept wave vector in the spectra store: (ky, kx < W/2, or any
@@ -119,6 +121,7 @@ hipError_t launch_step1(hipStream_t s, int pixel, const void* frames, int W, int
                         int nwg, int nbufs, int err_init);
 
 hipError_t launch_qexp(hipStream_t s, const float2* pilot, int np, int64_t nq, int32_t* qexp);
+hipError_t launch_qgrid(hipStream_t s, const int32_t* qexp, QTable qt, int H, int qgw, int8_t* qgrid);
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
 hipError_t launch_copy_i32(hipStream_t s, const int32_t* src, int32_t* dst, int n);
 

@@ -154,17 +154,16 @@ __global__ void __launch_bounds__(256) k_row(const PIX* __restrict__ frames, con
 
 // One value of the column transform into the spectra store: slot sl (group-
 // local index j = sl - s_lo), time t, at [j / QB][N][QB].  F16: complex FP16
-// scaled by 2^qexp[q] (round to nearest even), |value| > 65504 clamped and
-// counted.
+// scaled by 2^ex, ex the wave vector's exponent (round to nearest even),
+// |value| > 65504 clamped and counted.
 // NT: non-temporal stores (streamed past the L2 without displacing what it holds).
 template <int QB, bool F16, bool NT = false>
 __device__ __forceinline__ void put_spec(void* __restrict__ spec, int sl, int s_lo, int s_hi, int N, int t,
-                                         float2 val, int q, const int32_t* __restrict__ qexp, int& nsat) {
+                                         float2 val, int ex, int& nsat) {
   if (sl < s_lo || sl >= s_hi) return;
   const int j = sl - s_lo;
   const size_t at = ((size_t)(j / QB) * (size_t)N + (size_t)t) * QB + (j % QB);
   if constexpr (F16) {
-    const int ex = qexp[q];
     float re = ldexpf(val.x, ex), im = ldexpf(val.y, ex);
     const float lim = 65504.0f;
     if (!(fabsf(re) <= lim)) { re = copysignf(lim, re); ++nsat; }
@@ -188,7 +187,8 @@ __device__ __forceinline__ void put_spec(void* __restrict__ spec, int sl, int s_
 // in slot sbase[ky] + kx; the Nyquist value (ky, W/2) of a packed column sits
 // in slot sN + ky, or sbase[ky] + W/2 when sN < 0.  kxnyq = W/2 when column 0
 // of the intermediate carries R(0) + i R(W/2) (columns >= W/2 are then
-// padding), else -1.  qoff[ky] + kx is the wave vector (FP16 scale index).
+// padding), else -1.  F16: qgrid[ky qgw + kx] (qgw = W/2 + 1) is the FP16
+// exponent of wave vector (ky, kx).
 // Column item, in two parts.  col_load: this thread's E values of column
 // kx of one frame's intermediate (BYPASS: reads that skip the CU's L1, for
 // data written by other workgroups during the same launch).
@@ -216,9 +216,9 @@ template <int H, int E, int CW, int QB, bool F16, bool NT = false>
 __device__ __forceinline__ void col_fft_store(float2 (&v)[E], int tile, int t, int N,
                                               const int32_t* __restrict__ qoff, const int32_t* __restrict__ kxcnt,
                                               const int32_t* __restrict__ sbase, int sN, int s_lo, int s_hi,
-                                              int kxnyq, void* __restrict__ spec, const int32_t* __restrict__ qexp,
-                                              int& nsat, const float2* __restrict__ tw, int tws, float2* lds_col,
-                                              int tx) {
+                                              int kxnyq, void* __restrict__ spec, const int8_t* __restrict__ qgrid,
+                                              int qgw, int& nsat, const float2* __restrict__ tw, int tws,
+                                              float2* lds_col, int tx) {
   constexpr int T = H / E;
   const int c = tx % CW;
   const int tid = tx / CW;
@@ -230,6 +230,19 @@ __device__ __forceinline__ void col_fft_store(float2 (&v)[E], int tile, int t, i
     rs[e] = sbase[tid + e * T];
     rc[e] = kxcnt[tid + e * T];
   }
+  // F16: this thread's exponents, loaded before the transform so that their
+  // latency hides behind it; four bytes per register
+  uint32_t exq[(E + 3) / 4];
+  if constexpr (F16) {
+#pragma unroll
+    for (int i = 0; i < (E + 3) / 4; ++i) exq[i] = 0u;
+    if (kx < qgw) {
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        exq[e / 4] |= (uint32_t)(uint8_t)qgrid[(size_t)(tid + e * T) * qgw + kx] << (8 * (e % 4));
+    }
+  }
+  auto ex_of = [&](int e) { return F16 ? (int)(int8_t)(exq[e / 4] >> (8 * (e % 4))) : 0; };
   LdsView<CW> buf{lds_col + c};
   fft_forward<H, E, CW>(v, buf, tid, tw, tws);
   const int kxlim = kxnyq > 0 ? kxnyq : 0x7FFFFFFF;  // packing: columns >= W/2 are padding
@@ -237,7 +250,7 @@ __device__ __forceinline__ void col_fft_store(float2 (&v)[E], int tile, int t, i
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     if (kx < rc[e] && kx < kxlim && !(packed0 && kx == 0))
-      put_spec<QB, F16, NT>(spec, rs[e] + kx, s_lo, s_hi, N, t, v[e], F16 ? qoff[tid + e * T] + kx : 0, qexp, nsat);
+      put_spec<QB, F16, NT>(spec, rs[e] + kx, s_lo, s_hi, N, t, v[e], ex_of(e), nsat);
   }
   if (packed0) {
     // column 0 = FFT(R(0) + i R(W/2)): separate through LDS (every thread is
@@ -253,13 +266,13 @@ __device__ __forceinline__ void col_fft_store(float2 (&v)[E], int tile, int t, i
       for (int e = 0; e < E; ++e) {
         const int ky = tid + e * T;
         const float2 a = v[e], b = buf[ky == 0 ? 0 : H - ky];
-        const int q0 = F16 ? qoff[ky] : 0;
         if (0 < rc[e])
           put_spec<QB, F16, NT>(spec, rs[e], s_lo, s_hi, N, t,
-                            make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y)), q0, qexp, nsat);
+                            make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y)), ex_of(e), nsat);
         if (kxnyq < rc[e])
           put_spec<QB, F16, NT>(spec, sN >= 0 ? sN + ky : rs[e] + kxnyq, s_lo, s_hi, N, t,
-                            make_float2(0.5f * (a.y + b.y), -0.5f * (a.x - b.x)), q0 + kxnyq, qexp, nsat);
+                            make_float2(0.5f * (a.y + b.y), -0.5f * (a.x - b.x)),
+                            F16 ? (int)qgrid[(size_t)ky * qgw + kxnyq] : 0, nsat);
       }
     }
   }
@@ -271,7 +284,7 @@ __global__ void __launch_bounds__(CW * (H / E)) k_col(const float2* __restrict__
                                                       const int32_t* __restrict__ kxcnt,
                                                       const int32_t* __restrict__ sbase, int sN, int s_lo,
                                                       int s_hi, int kxnyq, void* __restrict__ spec,
-                                                      const int32_t* __restrict__ qexp, int32_t* sat,
+                                                      const int8_t* __restrict__ qgrid, int qgw, int32_t* sat,
                                                       const float2* __restrict__ tw, int tws) {
   extern __shared__ float2 lds_col[];
   float2 v[E];
@@ -279,7 +292,7 @@ __global__ void __launch_bounds__(CW * (H / E)) k_col(const float2* __restrict__
                             threadIdx.x / CW);
   int nsat = 0;
   col_fft_store<H, E, CW, QB, F16>(v, blockIdx.x, t0 + blockIdx.y, N, qoff, kxcnt, sbase, sN, s_lo, s_hi, kxnyq,
-                                   spec, qexp, nsat, tw, tws, lds_col, threadIdx.x);
+                                   spec, qgrid, qgw, nsat, tw, tws, lds_col, threadIdx.x);
   if (F16 && nsat > 0) atomicAdd(sat, nsat);
 }
 
@@ -357,7 +370,7 @@ __global__ void __launch_bounds__(16 * (W / E)) k_step1(const PIX* __restrict__ 
                                                          const int32_t* __restrict__ kxcnt,
                                                          const int32_t* __restrict__ sbase, int sN, int s_lo,
                                                          int s_hi, void* __restrict__ spec,
-                                                         const int32_t* __restrict__ qexp, int32_t* sat,
+                                                         const int8_t* __restrict__ qgrid, int qgw, int32_t* sat,
                                                          const float2* __restrict__ twW,
                                                          const float2* __restrict__ twH, int* __restrict__ ctl,
                                                          int maxslots, int nbufs, int lag) {
@@ -451,7 +464,7 @@ __global__ void __launch_bounds__(16 * (W / E)) k_step1(const PIX* __restrict__ 
       __syncthreads();
       if (threadIdx.x == 0) atomicAdd(&cols[k], 1);
       col_fft_store<H, E, CW, kSpecQB, F16, true>(v, tile, f, N, qoff, kxcnt, sbase, sN, s_lo, s_hi, kxnyq, spec,
-                                                  qexp, nsat, twH, 1, lds, tx);
+                                                  qgrid, qgw, nsat, twH, 1, lds, tx);
     }
   }
   if (F16 && nsat > 0) atomicAdd(sat, nsat);
@@ -474,8 +487,21 @@ __global__ void k_qexp(const float2* __restrict__ pilot, int np, int64_t nq, int
     const float m = frexpf(mx, &ex);  // mx = m 2^ex, m in [0.5, 1)
     const int c = (m == 0.5f) ? ex - 1 : ex;  // ceil(log2 mx)
     e = 11 - c;
+    // within int8 for the (ky, kx) grid; pilot maxima below 2^-89 (never
+    // reached by transforms of integer frames) keep the factor 2^100
+    e = e > 100 ? 100 : (e < -100 ? -100 : e);
   }
   qexp[q] = e;
+}
+
+// The exponents on the (ky, kx) grid the column transform stores from:
+// qgrid[ky qgw + kx] = qexp[qoff[ky] + kx] for kept kx, else 0.
+__global__ void k_qgrid(const int32_t* __restrict__ qexp, const int32_t* __restrict__ qoff,
+                        const int32_t* __restrict__ kxcnt, int H, int qgw, int8_t* __restrict__ qgrid) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= H * qgw) return;
+  const int ky = i / qgw, kx = i % qgw;
+  qgrid[i] = (int8_t)(kx < kxcnt[ky] ? qexp[qoff[ky] + kx] : 0);
 }
 
 __global__ void k_fill_i32s(int32_t* p, int64_t n, int32_t v) {
@@ -567,16 +593,17 @@ static hipError_t col_go(hipStream_t s, const float2* inter, int kxw, int ntiles
   static_assert(kSpecQB == 16, "the column transform is instantiated for blocks of 16");
   dim3 grid(ntiles, nframes);
   const size_t lds = (size_t)CW * H * sizeof(float2);
-  if (out.qexp != nullptr) {
+  if (out.qgrid != nullptr) {
     if (qb != kSpecQB) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_col<H, E, CW, 16, true>), grid, dim3(CW * T), lds, s, inter, kxw, t0, N, qt.qoff,
-                       qt.kxcnt, sm.sbase, sm.sN, s_lo, s_hi, kxnyq, out.spec, out.qexp, out.sat, tw, tws);
+                       qt.kxcnt, sm.sbase, sm.sN, s_lo, s_hi, kxnyq, out.spec, out.qgrid, out.qgw, out.sat, tw,
+                       tws);
   } else if (qb == kSpecQB) {
     hipLaunchKernelGGL((k_col<H, E, CW, 16, false>), grid, dim3(CW * T), lds, s, inter, kxw, t0, N, qt.qoff,
-                       qt.kxcnt, sm.sbase, sm.sN, s_lo, s_hi, kxnyq, out.spec, nullptr, nullptr, tw, tws);
+                       qt.kxcnt, sm.sbase, sm.sN, s_lo, s_hi, kxnyq, out.spec, nullptr, 0, nullptr, tw, tws);
   } else if (qb == 1) {
     hipLaunchKernelGGL((k_col<H, E, CW, 1, false>), grid, dim3(CW * T), lds, s, inter, kxw, t0, N, qt.qoff,
-                       qt.kxcnt, sm.sbase, sm.sN, s_lo, s_hi, kxnyq, out.spec, nullptr, nullptr, tw, tws);
+                       qt.kxcnt, sm.sbase, sm.sN, s_lo, s_hi, kxnyq, out.spec, nullptr, 0, nullptr, tw, tws);
   } else {
     return hipErrorInvalidValue;
   }
@@ -650,14 +677,14 @@ static hipError_t step1_go(hipStream_t s, const void* frames, int N, int pre, fl
                            int lag) {
   constexpr int E = 16, T = W / E, CW = 16;
   const size_t lds = std::max((size_t)CW * lds_len<true>(W) * sizeof(float2), (size_t)CW * W * sizeof(float2));
-  if (out.qexp != nullptr)
+  if (out.qgrid != nullptr)
     hipLaunchKernelGGL((k_step1<W, E, PIX, true>), dim3(nwg), dim3(CW * T), lds, s, (const PIX*)frames, N, pre,
                        bufs, kxw, ntiles, pack, kxnyq, qt.qoff, qt.kxcnt, sm.sbase, sm.sN, s_lo, s_hi, out.spec,
-                       out.qexp, out.sat, twW, twH, ctl, maxslots, nbufs, lag);
+                       out.qgrid, out.qgw, out.sat, twW, twH, ctl, maxslots, nbufs, lag);
   else
     hipLaunchKernelGGL((k_step1<W, E, PIX, false>), dim3(nwg), dim3(CW * T), lds, s, (const PIX*)frames, N, pre,
                        bufs, kxw, ntiles, pack, kxnyq, qt.qoff, qt.kxcnt, sm.sbase, sm.sN, s_lo, s_hi, out.spec,
-                       nullptr, nullptr, twW, twH, ctl, maxslots, nbufs, lag);
+                       nullptr, 0, nullptr, twW, twH, ctl, maxslots, nbufs, lag);
   return hipGetLastError();
 }
 
@@ -692,6 +719,13 @@ hipError_t launch_step1(hipStream_t s, int pixel, const void* frames, int W, int
       return hipErrorInvalidValue;
   }
 #undef S1_CASE
+}
+
+hipError_t launch_qgrid(hipStream_t s, const int32_t* qexp, QTable qt, int H, int qgw, int8_t* qgrid) {
+  const int n = H * qgw;
+  hipLaunchKernelGGL(k_qgrid, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, qexp, qt.qoff, qt.kxcnt, H, qgw,
+                     qgrid);
+  return hipGetLastError();
 }
 
 hipError_t launch_qexp(hipStream_t s, const float2* pilot, int np, int64_t nq, int32_t* qexp) {
