@@ -225,6 +225,12 @@ ddm_status ddm_structure_from_spectra(ddm_plan_t plan, const float* spectra_dev,
  * the plan's workspace (required); the choice is cached per (time length, N,
  * max_lag, storage) for the process and used by later calls.  Synchronises
  * the stream.  DDM_AUTOTUNE=off (environment) keeps the built-in shape.
+ * DDM_TUNE_CACHE=<file> (environment) keeps the results across processes: the
+ * file's lines for this device architecture and HIP runtime version are read
+ * at the first autotune, and every new timing is appended as a line
+ * "<arch> <runtime> <L> <N> <M> <f16> fourier <E> <qpw> <ms>" or
+ * "... direct <ms>".  DDM_LOG=1 (environment) prints one line per plan, batch,
+ * workspace and autotune decision on stderr.
  * Outputs (may be NULL): E, wave vectors per workgroup, estimated ms per call
  * of step two.  DDM_METHOD_AUTO plans also time the direct kernel on the same
  * spectra and keep the faster method (the ms is that method's); DDM_METHOD_DIRECT

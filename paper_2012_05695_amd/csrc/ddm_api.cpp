@@ -40,6 +40,26 @@ ddm_status hip_fail(hipError_t e, const char* what) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// DDM_LOG (environment, any value but 0): one line per plan, batch, workspace
+// and autotune decision on stderr, prefixed "[ddm]".
+bool log_on() {
+  static const bool on = [] {
+    const char* v = std::getenv("DDM_LOG");
+    return v != nullptr && v[0] != '\0' && std::strcmp(v, "0") != 0;
+  }();
+  return on;
+}
+
+void ddm_log(const char* fmt, ...) {
+  if (!log_on()) return;
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "[ddm] %s\n", buf);
+}
+
 }  // namespace
 
 namespace ddm {
@@ -233,10 +253,9 @@ int32_t ddm_abi_version(void) { return DDM_ABI_VERSION; }
 
 const char* ddm_last_error(void) { return g_err.c_str(); }
 
-ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
-  if (out == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "out is NULL");
-  *out = nullptr;
-  if (desc == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "desc is NULL");
+// Every descriptor rule that needs no device: the plan and batch constructors
+// refuse a descriptor before any HIP call.
+static ddm_status check_desc(const ddm_plan_desc* desc) {
   if (desc->struct_size != sizeof(ddm_plan_desc))
     return fail(DDM_ERR_INVALID_ARGUMENT, "desc.struct_size %u != %zu (header/library mismatch)",
                 desc->struct_size, sizeof(ddm_plan_desc));
@@ -262,6 +281,16 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
   if (desc->k2_max < -1) return fail(DDM_ERR_INVALID_ARGUMENT, "k2_max must be >= -1");
   if (desc->padding != DDM_PAD_POW2 && desc->padding != DDM_PAD_MINIMAL)
     return fail(DDM_ERR_INVALID_ARGUMENT, "padding must be DDM_PAD_POW2 or DDM_PAD_MINIMAL");
+  return DDM_OK;
+}
+
+ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
+  if (out == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (desc == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "desc is NULL");
+  ddm_status st0 = check_desc(desc);
+  if (st0 != DDM_OK) return st0;
+  const int W = desc->width, H = desc->height, N = desc->n_frames;
 
   ddm_plan_s* p = new (std::nothrow) ddm_plan_s();
   if (p == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -460,6 +489,16 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
     ddm_plan_destroy(p);
     return hip_fail(e, "copy stream setup");
   }
+  if (log_on()) {
+    size_t mn = 0, full = 0;
+    ddm_plan_workspace_size(p, &mn, &full);
+    ddm_log("plan %p: %dx%d %s x %d frames, %lld q, %d lags, %s spectra, step two %s%s (L %d), step one %s, "
+            "workspace min %.1f MB full %.1f MB",
+            (void*)p, W, H, desc->pixel == DDM_PIX_U8 ? "u8" : "u16", N, (long long)p->nq, p->M,
+            p->f16 ? "FP16" : "FP32", p->method == DDM_METHOD_DIRECT ? "direct" : "fourier",
+            desc->method == DDM_METHOD_AUTO ? " (auto: cost model)" : "", p->L,
+            p->fused ? "single launch" : "row + column kernels", mn / 1e6, full / 1e6);
+  }
   *out = p;
   g_err.clear();
   return DDM_OK;
@@ -542,6 +581,8 @@ ddm_status ddm_plan_workspace_size(ddm_plan_t p, size_t* min_bytes, size_t* full
   return DDM_OK;
 }
 
+static void partition(const ddm_plan_s* p, int* fb, int64_t* gblocks);
+
 ddm_status ddm_plan_set_workspace(ddm_plan_t p, void* ws, size_t bytes) {
   ddm_status st = check_plan(p);
   if (st != DDM_OK) return st;
@@ -552,11 +593,17 @@ ddm_status ddm_plan_set_workspace(ddm_plan_t p, void* ws, size_t bytes) {
   if (bytes < mn) return fail(DDM_ERR_OUT_OF_MEMORY, "workspace %zu bytes < minimum %zu", bytes, mn);
   p->ws = ws;
   p->ws_bytes = bytes;
+  if (log_on()) {
+    int fb;
+    int64_t gblocks;
+    partition(p, &fb, &gblocks);
+    const int64_t groups = (n_spec_blocks(p) + gblocks - 1) / gblocks;
+    ddm_log("plan %p: workspace %.1f MB: %d frames of row intermediate, %lld group(s) of wave vectors%s",
+            (void*)p, bytes / 1e6, fb, (long long)groups, groups > 1 ? " (every frame transformed per group)" : "");
+  }
   return DDM_OK;
 }
 
-// Split the workspace (after the FP16 auxiliaries) into the row intermediate
-// (fb frames) and the spectra store of one group (gblocks q-blocks).
 // Step two over slots [0, nslots) of a spectra store (layout qb: 16 blocked,
 // 1 plain) with the plan's method.
 static hipError_t launch_step_two(ddm_plan_s* p, const void* spec, int qb, int64_t nslots, const int32_t* qmap,
@@ -565,6 +612,8 @@ static hipError_t launch_step_two(ddm_plan_s* p, const void* spec, int qb, int64
   return launch_time(p->stream, p->L, spec, qb, nslots, p->N, p->M, p->twT, p->ramp, qmap, qexp, D, p->tshape);
 }
 
+// Split the workspace (after the FP16 auxiliaries) into the row intermediate
+// (fb frames) and the spectra store of one group (gblocks q-blocks).
 static void partition(const ddm_plan_s* p, int* fb, int64_t* gblocks) {
   const size_t blk = spec_block_bytes(p);
   const int64_t nb = n_spec_blocks(p);
@@ -815,6 +864,7 @@ static ddm_status scratch_address(void** out) {
     if (ptr == nullptr || ((uintptr_t)ptr & 255) != 0)
       return fail(DDM_ERR_HIP, "static scratch has no usable device address");
     g_scratch_ptr[dev] = ptr;
+    ddm_log("device %d: static scratch of %u bytes at %p", dev, (unsigned)DDM_NOALLOC_SCRATCH_BYTES, ptr);
   }
   *out = g_scratch_ptr[dev];
   return DDM_OK;
@@ -1160,6 +1210,67 @@ static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int, int>, std::tuple<int, int, double>> g_tune;
 static std::map<std::tuple<int, int, int, int>, double> g_tune_direct;  // direct-method ms
 
+// DDM_TUNE_CACHE (environment): a text file that keeps autotune results across
+// processes, one line per result, keyed by device architecture, HIP runtime
+// version, time length, N, max_lag and storage:
+//   <arch> <runtime> <L> <N> <M> <f16> fourier <E> <qpw> <ms>
+//   <arch> <runtime> <L> <N> <M> <f16> direct <ms>
+// Lines of other devices or runtimes are ignored; later lines win.  Read once
+// per process (under g_tune_mu), appended to after each timing.
+static bool g_tune_file_read = false;
+
+static std::string tune_device_tag() {
+  int dev = 0, rt = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "";
+  if (hipRuntimeGetVersion(&rt) != hipSuccess) rt = 0;
+  std::string arch = prop.gcnArchName;
+  for (char& c : arch)
+    if (c == ' ') c = '_';
+  return arch + " " + std::to_string(rt);
+}
+
+static void tune_file_read(const std::string& tag) {
+  const char* path = std::getenv("DDM_TUNE_CACHE");
+  if (g_tune_file_read || path == nullptr || tag.empty()) return;
+  g_tune_file_read = true;
+  FILE* f = std::fopen(path, "r");
+  if (f == nullptr) return;
+  char arch[128], kind[16];
+  int rt, L, N, M, f16;
+  char line[512];
+  int n = 0;
+  while (std::fgets(line, sizeof(line), f)) {
+    if (std::sscanf(line, "%127s %d %d %d %d %d %15s", arch, &rt, &L, &N, &M, &f16, kind) != 7) continue;
+    if (tag != std::string(arch) + " " + std::to_string(rt)) continue;
+    const auto key = std::make_tuple(L, N, M, f16);
+    int E, qpw;
+    double ms;
+    const char* rest = std::strstr(line, kind) + std::strlen(kind);
+    if (std::strcmp(kind, "fourier") == 0 && std::sscanf(rest, "%d %d %lf", &E, &qpw, &ms) == 3) {
+      g_tune[key] = std::make_tuple(E, qpw, ms);
+      ++n;
+    } else if (std::strcmp(kind, "direct") == 0 && std::sscanf(rest, "%lf", &ms) == 1) {
+      g_tune_direct[key] = ms;
+      ++n;
+    }
+  }
+  std::fclose(f);
+  ddm_log("autotune cache %s: %d result(s) for %s", path, n, tag.c_str());
+}
+
+static void tune_file_append(const std::string& tag, const std::string& line) {
+  const char* path = std::getenv("DDM_TUNE_CACHE");
+  if (path == nullptr || tag.empty()) return;
+  FILE* f = std::fopen(path, "a");
+  if (f == nullptr) {
+    ddm_log("autotune cache %s: cannot append", path);
+    return;
+  }
+  std::fprintf(f, "%s %s\n", tag.c_str(), line.c_str());
+  std::fclose(f);
+}
+
 ddm_status ddm_plan_autotune(ddm_plan_t p, int32_t* E_out, int32_t* qpw_out, double* ms_out) {
   ddm_status st = check_plan(p);
   if (st != DDM_OK) return st;
@@ -1172,8 +1283,10 @@ ddm_status ddm_plan_autotune(ddm_plan_t p, int32_t* E_out, int32_t* qpw_out, dou
   double best_ms = -1.0, direct_ms = -1.0;
   TimeShape best = p->tshape;
   bool have = !want_fourier, have_d = !want_direct;
+  const std::string tag = std::getenv("DDM_TUNE_CACHE") ? tune_device_tag() : std::string();
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
+    tune_file_read(tag);
     auto it = g_tune.find(key);
     if (want_fourier && it != g_tune.end()) {
       best.E = std::get<0>(it->second);
@@ -1249,12 +1362,28 @@ ddm_status ddm_plan_autotune(ddm_plan_t p, int32_t* E_out, int32_t* qpw_out, dou
     if (b) hipEventDestroy(b);
     if (e != hipSuccess) return hip_fail(e, "autotune");
     std::lock_guard<std::mutex> g(g_tune_mu);
-    if (!have) g_tune[key] = std::make_tuple(best.E, best.qpw, best_ms);
-    if (!have_d) g_tune_direct[key] = direct_ms;
+    const std::string k = std::to_string(p->L) + " " + std::to_string(p->N) + " " + std::to_string(p->M) + " " +
+                          std::to_string((int)p->f16);
+    char v[96];
+    if (!have) {
+      g_tune[key] = std::make_tuple(best.E, best.qpw, best_ms);
+      std::snprintf(v, sizeof(v), " fourier %d %d %.6f", best.E, best.qpw, best_ms);
+      tune_file_append(tag, k + v);
+    }
+    if (!have_d) {
+      g_tune_direct[key] = direct_ms;
+      std::snprintf(v, sizeof(v), " direct %.6f", direct_ms);
+      tune_file_append(tag, k + v);
+    }
   }
   p->tshape = best;
   if (p->d.method == DDM_METHOD_AUTO && best_ms > 0 && direct_ms > 0)
     p->method = direct_ms < best_ms ? DDM_METHOD_DIRECT : DDM_METHOD_FOURIER;
+  ddm_log("autotune plan %p (L %d, N %d, M %d, %s): transform E %d, %d per workgroup, %.3f ms%s; direct %.3f ms%s; "
+          "step two %s",
+          (void*)p, p->L, p->N, p->M, p->f16 ? "FP16" : "FP32", best.E, best.qpw, best_ms,
+          have ? " (cached)" : "", direct_ms, have_d ? " (cached)" : "",
+          p->method == DDM_METHOD_DIRECT ? "direct" : "fourier");
   if (E_out) *E_out = best.E;
   if (qpw_out) *qpw_out = best.qpw;
   if (ms_out) *ms_out = p->method == DDM_METHOD_DIRECT ? direct_ms : best_ms;
@@ -1326,9 +1455,15 @@ ddm_status ddm_batch_create(const ddm_plan_desc* descs, int32_t n, int32_t lanes
   *out = nullptr;
   if (descs == nullptr || n < 1) return fail(DDM_ERR_INVALID_ARGUMENT, "need at least one descriptor");
   if (lanes < 1 || lanes > 16) return fail(DDM_ERR_INVALID_ARGUMENT, "lanes must be in [1, 16]");
-  for (int i = 0; i < n; ++i)
+  for (int i = 0; i < n; ++i) {
+    const ddm_status st = check_desc(&descs[i]);
+    if (st != DDM_OK) {
+      const std::string why = g_err;
+      return fail(st, "stack %d: %s", i, why.c_str());
+    }
     if (descs[i].spectrum != DDM_SPEC_F32)
       return fail(DDM_ERR_UNSUPPORTED, "batched stacks use FP32 spectra (stack %d)", i);
+  }
   ddm_batch_s* b = new (std::nothrow) ddm_batch_s();
   if (b == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "host allocation failed");
   b->magic = kBatchMagic;
@@ -1417,7 +1552,10 @@ ddm_status ddm_batch_create(const ddm_plan_desc* descs, int32_t n, int32_t lanes
   for (int l = 0; l < lanes; ++l) {
     b->lane_off.push_back(off);
     off += b->lane_bytes[l];
+    ddm_log("batch %p: lane %d holds %.1f MB of workspace", (void*)b, l, b->lane_bytes[l] / 1e6);
   }
+  for (int i = 0; i < n; ++i) ddm_log("batch %p: stack %d -> plan %p, lane %d", (void*)b, i, (void*)b->plans[i],
+                                      b->lane_of[i]);
   *out = b;
   g_err.clear();
   return DDM_OK;
