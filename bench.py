@@ -51,6 +51,9 @@ def parse():
                     help="only copy a 1 GiB buffer 3 times (HBM byte-counter calibration)")
     ap.add_argument("--kernel-only", default=None,
                     help="run only this many steps and nothing else (for profilers)")
+    ap.add_argument("--direct-lags", type=int, default=0,
+                    help="with --kernel-only: step two by direct differences for this many lags "
+                         "(profiles of the direct kernel; never a bench line)")
     return ap.parse_args()
 
 
@@ -401,6 +404,9 @@ def batched_leg(n_stacks, log):
 
 def main():
     args = parse()
+    if args.direct_lags and args.kernel_only is None:
+        print("bench.py: --direct-lags is for --kernel-only profiling runs", file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the path shards over q across GPUs "
               "but no multi-GPU run exists); use --gpus 1", file=sys.stderr)
@@ -423,7 +429,10 @@ def main():
           flush=True)
     frames = synth.make(recipe, device="cuda")
     torch.cuda.synchronize()
-    plan = api.Plan(W, H, N, pixel=recipe["pixel"])
+    if args.direct_lags:
+        plan = api.Plan(W, H, N, pixel=recipe["pixel"], max_lag=args.direct_lags, method="direct")
+    else:
+        plan = api.Plan(W, H, N, pixel=recipe["pixel"])
     plan.allocate_workspace()
     M, nq = plan.max_lag, plan.n_q
     D = torch.empty((nq, M), dtype=torch.float32, device="cuda")
