@@ -15,7 +15,8 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("W,H,N,pixel,batch_frames,kw", [(256, 256, 300, "u16", 3, {}), (96, 64, 77, "u8", 5, {}),
                                                         (64, 64, 128, "u8", 1, {"k2_max": 300, "max_lag": 60}),
-                                                        (512, 512, 200, "u16", 16, {})])
+                                                        (512, 512, 200, "u16", 16, {}),
+                                                        (96, 64, 77, "u16", 4, {"method": "direct", "max_lag": 20})])
 def test_host_frames_match_device_frames(gpu, W, H, N, pixel, batch_frames, kw):
     print("case: host frames", W, H, N, pixel, batch_frames, kw, flush=True)
     frames = synth.brownian_stack(W, H, N, max(4, W * H // 50), 1.5, 40.0, 300.0, 0.3, seed=N, pixel=pixel)
