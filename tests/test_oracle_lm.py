@@ -60,3 +60,24 @@ def test_sample_curves_interpolates_linearly():
     np.testing.assert_allclose(Y[1, [0, 3, 4]] * c[1], lags[[0, 3, 4]] ** 2, rtol=1e-15)
     assert c[2] == 1.0 and np.all(Y[2] == 0)
     assert np.isclose(Y[0].max(), 1.0)
+
+
+@pytest.mark.parametrize("A,B,tau,noise", [(1.0, 0.05, 30.0, 0.0), (7.5, 0.3, 2.5, 0.02), (0.2, 1.0, 900.0, 0.05)])
+def test_default_start_properties(A, B, tau, noise):
+    """The default start (the reading of the fit start: B0 = y_1 / c, A0 = 1 - B0 on the curve
+    scaled by its maximum c, tau0 = sqrt(m_1 m_K)) checked through the model it starts: at lag 0
+    it takes the first sample's value, for large lags it plateaus at the curve's maximum, and
+    its relaxation time lies halfway between the first and last lags on the log axis."""
+    r = np.random.default_rng(3)
+    y = lm.model((A, B, np.log(tau)), M) * (1 + noise * r.standard_normal(len(M)))
+    p0 = lm.default_init(y, M)
+    start = lambda m: lm.model(p0, np.asarray(m, dtype=np.float64))
+    assert start([0.0])[0] == pytest.approx(y[0], rel=1e-12)
+    assert start([1e9 * M[-1]])[0] == pytest.approx(y.max(), rel=1e-12)
+    assert np.exp(2 * p0[2]) == pytest.approx(M[0] * M[-1], rel=1e-12)
+    # a curve of zeros, and one with a non-finite maximum, take the scale 1
+    z = lm.default_init(np.zeros(len(M)), M)
+    assert z[0] == 1.0 and z[1] == 0.0
+    bad = y.copy()
+    bad[-1] = np.inf
+    assert lm.default_init(bad, M)[0] == pytest.approx(1.0 - y[0])
