@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--batched-stacks", type=int, default=64)
     ap.add_argument("--no-direct", action="store_true",
                     help="skip the direct-difference leg (step two by Eq. (1) against the time transform)")
+    ap.add_argument("--no-long", action="store_true",
+                    help="skip the long-stack leg (the bench frames' recipe at 16384 frames, direct differences)")
+    ap.add_argument("--long-lags", type=int, default=64)
     ap.add_argument("--learned-curves", type=int, default=1_000_000)
     ap.add_argument("--learned-epochs", type=int, default=30)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -575,6 +578,9 @@ def main():
         print("bench: direct-difference leg (max_lag and N sweeps against the time transform)", file=sys.stderr,
               flush=True)
         out["direct"] = direct_leg(frames, recipe["pixel"])
+    if not args.no_long:
+        print("bench: long-stack leg (16384 frames, direct differences)", file=sys.stderr, flush=True)
+        out["long_stack"] = long_stack_leg(recipe, args.long_lags)
     del frames, D
     plan.close()
     torch.cuda.empty_cache()
@@ -661,6 +667,38 @@ def direct_leg(frames, pixel, reps=3):
     torch.cuda.empty_cache()
     return {"workload": "%dx%d frames of the bench stack, FP32 spectra store; step two only" % (W, H),
             "max_lag_sweep_at_N%d" % N: lags, "all_lags_sweep": sweep}
+
+
+def long_stack_leg(recipe, M, N=16384, steps=3):
+    """The bench frames' recipe at N = 16384 frames (the paper's longest stacks),
+    beyond the time transform's lengths: step one, then step two by direct
+    differences for M lags, timed over whole steps (the frames resident in HBM)."""
+    import torch
+    from paper_2012_05695_amd import api, synth
+    W, H = recipe["W"], recipe["H"]
+    frames = synth.make(recipe, device="cuda", N=N)
+    plan = api.Plan(W, H, N, pixel=recipe["pixel"], max_lag=M, method="direct")
+    plan.allocate_workspace()
+    D = plan.structure_function(frames)
+    torch.cuda.synchronize()
+    plan.set_profiling(["step1", "row", "col", "time"])
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(steps):
+        plan.structure_function(frames, out=D)
+    ev[1].record()
+    torch.cuda.synchronize()
+    plan.status()
+    ms = ev[0].elapsed_time(ev[1]) / steps
+    prof = {k: plan.profile(k) for k in ("step1", "row", "col", "time")}
+    per = {("direct" if k == "time" else k): v[0] / steps for k, v in prof.items() if v[1] > 0}
+    nq = plan.n_q
+    plan.close()
+    del frames, D
+    torch.cuda.empty_cache()
+    return {"workload": "%dx%d %s x %d frames, %d lags, step two by direct differences" % (W, H, recipe["pixel"], N, M),
+            "ms_per_stack": ms, "frames_per_s": N / (ms * 1e-3), "kernel_ms": per,
+            "algorithmic_bytes": N * H * W * (2 if recipe["pixel"] == "u16" else 1) + 2 * nq * N * 8 + nq * M * 4}
 
 
 def finish(args, out, frames_cpu, nq):
