@@ -145,3 +145,19 @@ def test_direct_in_batch_and_noalloc(gpu):
         if i == 0:
             assert torch.equal(Db[i], p.structure_function_noalloc(fr[i]))
     assert batch.status() == [L.DDM_OK] * 3
+
+
+def test_direct_paper_shape_sampled(gpu):
+    """The bench workload (512 x 512 u16 x 1024 frames) with 16 lags by direct
+    differences, the launch shape the bench times: kx columns {0, 1, 255, 256}
+    (the packed column pair and the Nyquist column included), every ky."""
+    say("case: direct 512x512x1024 u16, 16 lags, kx columns {0, 1, 255, 256}")
+    frames = synth.make(synth.PAPER, device="cuda")
+    plan = gpu.Plan(512, 512, 1024, max_lag=16, method="direct")
+    D = plan.structure_function(frames)
+    torch.cuda.synchronize()
+    Dg = D.cpu().numpy()
+    Do, rows = oracle_D(frames.cpu().numpy(), max_lag=16, kx_subset=[0, 1, 255, 256])
+    e = per_q_error(Dg[rows], Do)
+    say("512x512x1024 direct (%d q):" % len(rows), describe(e))
+    assert e.max() <= TOL_F32
