@@ -312,7 +312,7 @@ def copy_bandwidth():
     return 2 * (1 << 30) / (ms * 1e-3) / 1e9
 
 
-def batched_leg(n_stacks, log):
+def batched_leg(n_stacks, log, lanes=4):
     """a7: stacks of mixed shapes (W = H in {128, 256, 384, 512, 1024}, N log-uniform in
     [256, 4096], D0 log-uniform in [0.01, 10], 2000 spots per 512x512, uint16) in one graph
     launch, against the same stacks as a loop of single-plan calls on one stream."""
@@ -334,7 +334,7 @@ def batched_leg(n_stacks, log):
     total = sum(n for _, _, n in shapes)
     log("batched leg: %d stacks, %d frames, %.1f GB of frames" %
         (n_stacks, total, sum(f.numel() * 2 for f in frames) / 1e9))
-    batch = api.Batch(shapes, lanes=4)
+    batch = api.Batch(shapes, lanes=lanes)
     batch.allocate_workspace()
     # integer |q| bins (b = round |k|) of every stack, computed inside the graph
     thr = [api.integer_bin_thresholds(int(w * 0.7072) + 2) for (w, _, _) in shapes]
@@ -379,7 +379,7 @@ def batched_leg(n_stacks, log):
     torch.cuda.empty_cache()
     # the same batch with minimal padding (time transforms of the smallest 2^k
     # or 3 * 2^k >= N) instead of powers of two (the length Eq. (B4) prints)
-    b2 = api.Batch(shapes, lanes=4, padding="minimal")
+    b2 = api.Batch(shapes, lanes=lanes, padding="minimal")
     b2.allocate_workspace()
     for i, t in enumerate(thr):
         b2.set_bins(i, t)
