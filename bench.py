@@ -54,6 +54,8 @@ def parse():
                     help="only copy a 1 GiB buffer 3 times (HBM byte-counter calibration)")
     ap.add_argument("--kernel-only", default=None,
                     help="run only this many steps and nothing else (for profilers)")
+    ap.add_argument("--f16", action="store_true",
+                    help="with --kernel-only: the FP16 per-q-scaled spectra store (profiles; never a bench line)")
     ap.add_argument("--direct-lags", type=int, default=0,
                     help="with --kernel-only: step two by direct differences for this many lags "
                          "(profiles of the direct kernel; never a bench line)")
@@ -407,8 +409,8 @@ def batched_leg(n_stacks, log, lanes=4):
 
 def main():
     args = parse()
-    if args.direct_lags and args.kernel_only is None:
-        print("bench.py: --direct-lags is for --kernel-only profiling runs", file=sys.stderr)
+    if (args.direct_lags or args.f16) and args.kernel_only is None:
+        print("bench.py: --direct-lags and --f16 are for --kernel-only profiling runs", file=sys.stderr)
         sys.exit(2)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the path shards over q across GPUs "
@@ -432,10 +434,12 @@ def main():
           flush=True)
     frames = synth.make(recipe, device="cuda")
     torch.cuda.synchronize()
+    spectrum = "f16" if args.f16 else "f32"
     if args.direct_lags:
-        plan = api.Plan(W, H, N, pixel=recipe["pixel"], max_lag=args.direct_lags, method="direct")
+        plan = api.Plan(W, H, N, pixel=recipe["pixel"], spectrum=spectrum, max_lag=args.direct_lags,
+                        method="direct")
     else:
-        plan = api.Plan(W, H, N, pixel=recipe["pixel"])
+        plan = api.Plan(W, H, N, pixel=recipe["pixel"], spectrum=spectrum)
     plan.allocate_workspace()
     M, nq = plan.max_lag, plan.n_q
     D = torch.empty((nq, M), dtype=torch.float32, device="cuda")
