@@ -247,9 +247,13 @@ ddm_status ddm_plan_method(ddm_plan_t plan, int32_t* method);
  * stacks at once).  One plan per stack (FP32 spectra); stacks are spread over
  * `lanes` internal streams, largest first onto the least loaded one; each
  * lane owns a slice of the caller's workspace, reused by its stacks in turn.
- * The first call (and any call with different pointers) captures the whole
- * fork/join sequence into a HIP graph; every call is one graph launch on
- * `stream`.  Results per stack equal ddm_structure_function bit for bit.
+ * A call with a new set of frame / output pointers captures the whole
+ * fork/join sequence into a HIP graph; the batch keeps the graphs of up to 4
+ * pointer sets (a caller alternating output buffers replays them; the least
+ * recently launched is replaced), and every call is one graph launch on
+ * `stream`.  Changing the workspace, the bins or the launch shapes (autotune)
+ * drops the graphs.  Results per stack equal ddm_structure_function bit for
+ * bit.
  * ------------------------------------------------------------------------- */
 typedef struct ddm_batch_s* ddm_batch_t;
 

@@ -1408,11 +1408,20 @@ struct ddm_batch_s {
   std::vector<size_t> lane_bytes, lane_off;
   hipEvent_t fork;
   std::vector<hipEvent_t> join;
-  hipGraphExec_t exec;
-  std::vector<const void*> g_frames;
-  std::vector<float*> g_D;
-  std::vector<double*> g_Dbar;
-  std::vector<int64_t*> g_counts;
+  // captured graphs, one per set of caller pointers (a caller that alternates
+  // output buffers replays instead of capturing again); the least recently
+  // launched is replaced when a new set arrives and the cache is full
+  struct Graph {
+    hipGraphExec_t exec;
+    std::vector<const void*> frames;
+    std::vector<float*> D;
+    std::vector<double*> Dbar;
+    std::vector<int64_t*> counts;
+    uint64_t used;  // the call that last launched it
+  };
+  static constexpr size_t kGraphs = 4;
+  std::vector<Graph> graphs;
+  uint64_t calls;
   void* ws;
   size_t ws_bytes;
   // per-stack step-one error flags: written by the graph into flags_d, copied
@@ -1433,8 +1442,14 @@ static ddm_status check_batch(ddm_batch_t b) {
   return DDM_OK;
 }
 
+// Destroy every captured graph (pointers, workspace or bins changed).
+static void batch_drop_graphs(ddm_batch_s* b) {
+  for (auto& g : b->graphs) hipGraphExecDestroy(g.exec);
+  b->graphs.clear();
+}
+
 static void batch_free(ddm_batch_s* b) {
-  if (b->exec) hipGraphExecDestroy(b->exec);
+  batch_drop_graphs(b);
   for (int i = 0; i < kReadback; ++i)
     if (b->fl_ev[i]) hipEventDestroy(b->fl_ev[i]);
   if (b->flags_h) hipHostFree(b->flags_h);
@@ -1469,7 +1484,7 @@ ddm_status ddm_batch_create(const ddm_plan_desc* descs, int32_t n, int32_t lanes
   b->magic = kBatchMagic;
   b->stream = (hipStream_t)stream;
   b->fork = nullptr;
-  b->exec = nullptr;
+  b->calls = 0;
   b->ws = nullptr;
   b->ws_bytes = 0;
   b->root = nullptr;
@@ -1605,10 +1620,7 @@ ddm_status ddm_batch_set_workspace(ddm_batch_t b, void* ws, size_t bytes) {
   }
   b->ws = ws;
   b->ws_bytes = bytes;
-  if (b->exec) {  // the captured graph refers to the old workspace
-    hipGraphExecDestroy(b->exec);
-    b->exec = nullptr;
-  }
+  batch_drop_graphs(b);  // the captured graphs refer to the old workspace
   return DDM_OK;
 }
 
@@ -1620,10 +1632,7 @@ ddm_status ddm_batch_autotune(ddm_batch_t b) {
     st = ddm_plan_autotune(p, nullptr, nullptr, nullptr);
     if (st != DDM_OK) return st;
   }
-  if (b->exec) {
-    hipGraphExecDestroy(b->exec);
-    b->exec = nullptr;
-  }
+  batch_drop_graphs(b);  // the captured graphs hold the old launch shapes
   return DDM_OK;
 }
 
@@ -1702,10 +1711,7 @@ ddm_status ddm_batch_set_bins(ddm_batch_t b, int32_t stack, const int64_t* thr, 
   if ((st = upload_thresholds(p, thr, n_bins)) != DDM_OK) return st;
   if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return hip_fail(e, "batch bins");
   p->batch_nbins = n_bins;
-  if (b->exec) {  // the captured graph holds the old bins
-    hipGraphExecDestroy(b->exec);
-    b->exec = nullptr;
-  }
+  batch_drop_graphs(b);  // the captured graphs refer to the old bins
   return DDM_OK;
 }
 
@@ -1745,15 +1751,24 @@ static ddm_status batch_run(ddm_batch_t b, const void* const* frames, float* con
     if (frames[i] == nullptr || D[i] == nullptr) return fail(DDM_ERR_INVALID_ARGUMENT, "stack %zu: NULL pointer", i);
     if (((uintptr_t)frames[i] & 15) != 0) return fail(DDM_ERR_INVALID_ARGUMENT, "stack %zu: frames not 16-byte aligned", i);
   }
-  bool same = b->exec != nullptr && b->g_frames.size() == n;
-  for (size_t i = 0; same && i < n; ++i) {
-    same = b->g_frames[i] == frames[i] && b->g_D[i] == D[i] &&
-           b->g_Dbar[i] == (Dbar ? Dbar[i] : nullptr) && b->g_counts[i] == (counts ? counts[i] : nullptr);
+  ddm_batch_s::Graph* gr = nullptr;
+  for (auto& g : b->graphs) {
+    bool same = true;
+    for (size_t i = 0; same && i < n; ++i)
+      same = g.frames[i] == frames[i] && g.D[i] == D[i] && g.Dbar[i] == (Dbar ? Dbar[i] : nullptr) &&
+             g.counts[i] == (counts ? counts[i] : nullptr);
+    if (same) {
+      gr = &g;
+      break;
+    }
   }
-  if (!same) {
-    if (b->exec) {
-      hipGraphExecDestroy(b->exec);
-      b->exec = nullptr;
+  if (gr == nullptr) {
+    if (b->graphs.size() >= ddm_batch_s::kGraphs) {  // replace the least recently launched
+      size_t lru = 0;
+      for (size_t k = 1; k < b->graphs.size(); ++k)
+        if (b->graphs[k].used < b->graphs[lru].used) lru = k;
+      hipGraphExecDestroy(b->graphs[lru].exec);
+      b->graphs.erase(b->graphs.begin() + (std::ptrdiff_t)lru);
     }
     hipError_t e = hipStreamBeginCapture(b->root, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
@@ -1765,25 +1780,29 @@ static ddm_status batch_run(ddm_batch_t b, const void* const* frames, float* con
       return st;
     }
     if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
-    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    ddm_batch_s::Graph ng;
+    ng.exec = nullptr;
+    e = hipGraphInstantiate(&ng.exec, g, nullptr, nullptr, 0);
     hipGraphDestroy(g);
-    if (e != hipSuccess) {
-      b->exec = nullptr;
-      return hip_fail(e, "hipGraphInstantiate");
-    }
-    b->g_frames.assign(frames, frames + n);
-    b->g_D.assign(D, D + n);
-    b->g_Dbar.assign(n, nullptr);
-    b->g_counts.assign(n, nullptr);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    ng.frames.assign(frames, frames + n);
+    ng.D.assign(D, D + n);
+    ng.Dbar.assign(n, nullptr);
+    ng.counts.assign(n, nullptr);
     for (size_t i = 0; i < n; ++i) {
-      if (Dbar) b->g_Dbar[i] = Dbar[i];
-      if (counts) b->g_counts[i] = counts[i];
+      if (Dbar) ng.Dbar[i] = Dbar[i];
+      if (counts) ng.counts[i] = counts[i];
     }
+    b->graphs.push_back(std::move(ng));
+    gr = &b->graphs.back();
+    ddm_log("batch %p: captured graph %zu of %zu for a new set of pointers", (void*)b, b->graphs.size(),
+            ddm_batch_s::kGraphs);
   }
+  gr->used = ++b->calls;
   // order after the caller's stream, launch, and order the caller's stream after it
   hipError_t e = hipEventRecord(b->in_ev, b->stream);
   if (e == hipSuccess) e = hipStreamWaitEvent(b->root, b->in_ev, 0);
-  if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->root);
+  if (e == hipSuccess) e = hipGraphLaunch(gr->exec, b->root);
   if (e == hipSuccess) e = hipEventRecord(b->out_ev, b->root);
   if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->out_ev, 0);
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");

@@ -101,3 +101,24 @@ def test_batch_bins_match_radial_average(gpu):
         c_o = np.bincount(b[b >= 0], weights=w[b >= 0], minlength=len(thr[i]) - 1).astype(np.int64)
         np.testing.assert_array_equal(cnt[i].cpu().numpy(), c_o)
     assert batch.status() == [0] * len(SHAPES)
+
+
+def test_batch_graph_cache_alternating_outputs(gpu):
+    """Output buffers alternated between calls replay their own captured graphs;
+    more pointer sets than the batch keeps replace the least recently launched
+    graph. Every call's results equal the first call's bit for bit."""
+    print("case: batch graph cache, alternating and evicted output sets", flush=True)
+    shapes = [(64, 64, 100), (96, 48, 60), (128, 128, 40)]
+    fr = [synth.uniform_stack(w, h, n, seed=40 + i).cuda() for i, (w, h, n) in enumerate(shapes)]
+    batch = gpu.Batch(shapes, lanes=2)
+    ref = [d.clone() for d in batch.structure_function(fr)]
+    sets = [[torch.full_like(d, float("nan")) for d in ref] for _ in range(6)]
+    order = [0, 1, 0, 1, 2, 3, 4, 5, 0, 1, 5]  # sets 0 and 1 are evicted by 2..5, then captured again
+    for k in order:
+        for d in sets[k]:
+            d.fill_(float("nan"))
+        out = batch.structure_function(fr, sets[k])
+        torch.cuda.synchronize()
+        for i in range(len(shapes)):
+            assert torch.equal(out[i], ref[i]), (k, i)
+    assert batch.status() == [0] * len(shapes)
