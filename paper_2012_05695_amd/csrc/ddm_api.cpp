@@ -81,13 +81,13 @@ constexpr size_t kInterTargetBytes = 128u << 20;  // row-transform intermediate 
 constexpr int kReadback = 4;                      // calls in flight before the host waits
 
 // Step two's cost model: the direct method evaluates N M - M (M - 1) / 2
-// difference pairs per wave vector at four vector operations each; the time
-// transform of length L costs about 16 L log2 L operations per wave vector
-// (three L-point transforms with their pre- and post-processing).
+// difference pairs per wave vector; the time transform of length L costs a
+// time proportional to L log2 L per wave vector.  The constant is the measured
+// crossover at 512 x 512 x 1024 (L = N = 1024): the transform is faster from
+// 48 lags on.
 bool direct_cheaper(int N, int M, int L) {
   const double pairs = (double)N * M - 0.5 * (double)M * (M - 1);
-  const double fourier = 16.0 * L * std::log2((double)L);
-  return 4.0 * pairs < fourier;
+  return pairs < 4.6 * L * std::log2((double)L);
 }
 
 }  // namespace
