@@ -127,8 +127,10 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out);
 ddm_status ddm_plan_destroy(ddm_plan_t plan);
 
 /* n_q: number of kept wave vectors (rows of D).  max_lag: M.  n2: the
- * zero-padded time-FFT length of Eq. (B4), log2 N2 = ceil(log2 N) + 1.
- * Any output pointer may be NULL. */
+ * zero-padded time-FFT length that Eq. (B4) prints, log2 N2 = ceil(log2 N) + 1
+ * (whatever the plan's padding and method; the minimal padding's length is
+ * 2 L with L the smallest 2^k or 3 * 2^k >= N).  Any output pointer may be
+ * NULL. */
 ddm_status ddm_plan_query(ddm_plan_t plan, int64_t* n_q, int32_t* max_lag, int32_t* n2);
 
 /* Host arrays of n_q entries: kx and signed ky of every row of D, in q order. */
@@ -216,9 +218,10 @@ ddm_status ddm_plan_fp16_saturations(ddm_plan_t plan, int64_t* count);
  * workspace.  Used to check step one on its own. */
 ddm_status ddm_image_spectra(ddm_plan_t plan, const void* frames_dev, float* spectra_dev);
 
-/* Step two only (Appendix B): spectra_dev [n_q][N] complex float32 (as written
- * by ddm_image_spectra, or any time series) -> D_dev [n_q][M] float32.
- * Needs no workspace. */
+/* Step two only, with the plan's method (the time transform of Appendix B, or
+ * Eq. (1) directly): spectra_dev [n_q][N] complex float32 (as written by
+ * ddm_image_spectra, or any time series) -> D_dev [n_q][M] float32.  Needs no
+ * workspace. */
 ddm_status ddm_structure_from_spectra(ddm_plan_t plan, const float* spectra_dev, float* D_dev);
 
 /* Pick the time-kernel launch shape (values per thread, wave vectors per
