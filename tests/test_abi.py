@@ -99,6 +99,21 @@ def test_host_only_calls(libddm_path):
     d.method, d.n_frames = _lib.DDM_METHOD_DIRECT, 65537
     assert lib.ddm_plan_create(ctypes.byref(d), ctypes.byref(h)) == _lib.DDM_ERR_UNSUPPORTED
     assert lib.ddm_plan_method(None, None) == _lib.DDM_ERR_INVALID_ARGUMENT
+    # batches: every stack descriptor is checked before any HIP call, and
+    # batched stacks take the FP32 spectra store only
+    descs = (_lib.PlanDesc * 2)()
+    for i in range(2):
+        lib.ddm_plan_desc_init(ctypes.byref(descs[i]))
+        descs[i].width, descs[i].height, descs[i].n_frames = 64, 64, 16
+    descs[1].spectrum = _lib.DDM_SPEC_F16_QSCALED
+    b = ctypes.c_void_p(1234)
+    assert lib.ddm_batch_create(descs, 2, 2, None, ctypes.byref(b)) == _lib.DDM_ERR_UNSUPPORTED
+    assert b.value is None and b"stack 1" in lib.ddm_last_error()
+    descs[1].spectrum = _lib.DDM_SPEC_F32
+    descs[1].n_frames = 1
+    assert lib.ddm_batch_create(descs, 2, 2, None, ctypes.byref(b)) == _lib.DDM_ERR_INVALID_ARGUMENT
+    assert b"stack 1" in lib.ddm_last_error()
+    assert lib.ddm_batch_create(descs, 2, 0, None, ctypes.byref(b)) == _lib.DDM_ERR_INVALID_ARGUMENT
     assert lib.ddm_plan_destroy(None) == _lib.DDM_OK
     assert lib.ddm_structure_function(None, None, None) == _lib.DDM_ERR_INVALID_ARGUMENT
 
