@@ -161,3 +161,29 @@ def test_direct_paper_shape_sampled(gpu):
     e = per_q_error(Dg[rows], Do)
     say("512x512x1024 direct (%d q):" % len(rows), describe(e))
     assert e.max() <= TOL_F32
+
+
+def test_direct_lags_per_lane_same_bits(gpu, tmp_path):
+    """8 and 16 lags per lane (DDM_DIRECT_LAGS, read once per process, so the
+    other setting runs in a child process) sum each lag's pairs in the same
+    time order: the same bits."""
+    import os
+    import subprocess
+    say("case: direct, 8 vs 16 lags per lane, 128x128x300, 64 and 200 lags")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    frames = synth.brownian_stack(128, 128, 300, 400, 1.5, 40.0, 300.0, 0.3, seed=77)
+    ref = {M: gpu.Plan(128, 128, 300, max_lag=M, method="direct").structure_function(frames.cuda()).cpu()
+           for M in (64, 200)}
+    src, dst = str(tmp_path / "f.pt"), str(tmp_path / "d.pt")
+    torch.save(frames, src)
+    child = ("import sys; sys.path.insert(0, %r)\n"
+             "import torch\nfrom paper_2012_05695_amd import api\n"
+             "f = torch.load(sys.argv[1], weights_only=True).cuda()\n"
+             "torch.save({M: api.Plan(128, 128, 300, max_lag=M, method='direct').structure_function(f).cpu()"
+             " for M in (64, 200)}, sys.argv[2])\n" % root)
+    r = subprocess.run([sys.executable, "-c", child, src, dst], capture_output=True, text=True,
+                       env=dict(os.environ, DDM_DIRECT_LAGS="8"), timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    got = torch.load(dst, weights_only=True)
+    for M in (64, 200):
+        assert torch.equal(got[M], ref[M]), M
