@@ -82,10 +82,10 @@ typedef enum ddm_padding { DDM_PAD_POW2 = 0, DDM_PAD_MINIMAL = 1 } ddm_padding;
  *   applied to the stored spectra: the spectrum of a difference image is the
  *   difference of the spectra): O(N M) per wave vector.  FP32 differences,
  *   FP32 sums over 64 time points added into FP64 totals.  Cheaper than
- *   FOURIER when few lags are wanted (at N = 1024 below about 48); the only
- *   method for N above 8192 (up to 65536).
+ *   FOURIER when few lags are wanted (at 512 x 512 x 1024 below about 52); the
+ *   only method for N above 8192 (up to 65536).
  * AUTO: DIRECT where a cost model (N M - M (M - 1) / 2 difference pairs
- *   against 4.6 L log2 L for the transform of length L, the constant from the
+ *   against 5.2 L log2 L for the transform of length L, the constant from the
  *   measured crossover) expects it to be faster, else FOURIER;
  *   ddm_plan_autotune replaces the model's choice by a timing of both.
  *   ddm_plan_method reports the choice. */

@@ -83,11 +83,13 @@ constexpr int kReadback = 4;                      // calls in flight before the 
 // Step two's cost model: the direct method evaluates N M - M (M - 1) / 2
 // difference pairs per wave vector; the time transform of length L costs a
 // time proportional to L log2 L per wave vector.  The constant is the measured
-// crossover at 512 x 512 x 1024 (L = N = 1024): the transform is faster from
-// 48 lags on.
+// crossover at 512 x 512 frames: direct faster at 48 lags and the transform
+// faster at 56 for both N = 512 and N = 1024 (at 256 x 256, with fewer wave
+// vectors, direct stays faster to about 80 lags at N = 2048 and 96 at 4096;
+// the model keeps the larger frames' constant there, and autotune times both).
 bool direct_cheaper(int N, int M, int L) {
   const double pairs = (double)N * M - 0.5 * (double)M * (M - 1);
-  return pairs < 4.6 * L * std::log2((double)L);
+  return pairs < 5.2 * L * std::log2((double)L);
 }
 
 }  // namespace

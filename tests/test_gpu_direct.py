@@ -187,3 +187,41 @@ def test_direct_lags_per_lane_same_bits(gpu, tmp_path):
     got = torch.load(dst, weights_only=True)
     for M in (64, 200):
         assert torch.equal(got[M], ref[M]), M
+
+
+def test_direct_time_ranges_match_oracle(gpu, tmp_path):
+    """The split of the base points into 2 or 4 ranges of 64-point chunks
+    (ranges past N - m left empty for the high lag tiles) against a single
+    range (DDM_DIRECT_PARTS=1, read once per process, so in a child process)
+    and against the oracle: 32 x 32 x 300 (4 ranges, every lag), 64 x 48 x 1000
+    (4 ranges, 37 lags), 96 x 96 x 700 FP16 (4 ranges, 100 lags), 48 x 32 x 150
+    (2 ranges: three chunks, every lag)."""
+    import os
+    import subprocess
+    cases = [(32, 32, 300, 300, "f32"), (64, 48, 1000, 37, "f32"), (96, 96, 700, 100, "f16"),
+             (48, 32, 150, 150, "f32")]
+    say("case: direct time ranges vs one range", cases)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    frames = [synth.brownian_stack(W, H, N, max(4, W * H // 30), 1.5, 40.0, 200.0, 0.3, seed=N + 7, pixel="u16")
+              for (W, H, N, M, sp) in cases]
+    src, dst = str(tmp_path / "f.pt"), str(tmp_path / "d.pt")
+    torch.save(frames, src)
+    child = ("import sys; sys.path.insert(0, %r)\n"
+             "import torch\nfrom paper_2012_05695_amd import api\n"
+             "fr = torch.load(sys.argv[1], weights_only=True)\n"
+             "cases = %r\n"
+             "torch.save([api.Plan(W, H, N, max_lag=M, method='direct', spectrum=sp).structure_function(f.cuda()).cpu()"
+             " for (W, H, N, M, sp), f in zip(cases, fr)], sys.argv[2])\n" % (root, cases))
+    r = subprocess.run([sys.executable, "-c", child, src, dst], capture_output=True, text=True,
+                       env=dict(os.environ, DDM_DIRECT_PARTS="1"), timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    one = torch.load(dst, weights_only=True)
+    for (W, H, N, M, sp), f, D1 in zip(cases, frames, one):
+        D = gpu.Plan(W, H, N, max_lag=M, method="direct", spectrum=sp).structure_function(f.cuda()).cpu()
+        Do, _ = oracle_D(f.numpy(), max_lag=M)
+        tol = 5e-3 if sp == "f16" else TOL_F32
+        e, e1 = per_q_error(D.numpy(), Do), per_q_error(D1.numpy(), Do)
+        say("ranges", (W, H, N, M, sp), "default", describe(e), "one range", describe(e1))
+        assert e.max() <= tol and e1.max() <= tol
+        # the FP64 totals of FP32 chunk sums: the two orders agree to FP64 rounding
+        assert per_q_error(D.numpy(), D1.numpy().astype(np.float64)).max() <= 1e-6
