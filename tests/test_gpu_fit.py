@@ -110,3 +110,50 @@ def test_fit_best_start(gpu):
         po, co, io, fo = lm.lm_fit(Y[i].astype(np.float64), mm, p0)
         cg = np.sum((lm.model((pb[i, 0], pb[i, 1], np.log(pb[i, 2])), mm) - Y[i]) ** 2)
         assert cg <= co * (1 + 1e-4) + 1e-10, (i, cg, co)
+
+
+def test_lm_many_curves_per_lane(gpu):
+    """250,000 curves (more than one per lane of the resident waves, so lanes
+    take further curves as theirs finish), mixed clean, noisy and flat so that
+    the lanes of a wave finish at different iterations: every curve gets the
+    same bits as in a call of 2,000 curves (one curve per lane), from the
+    default start and with a start plus the refit pass, and sampled curves
+    reach the FP64 oracle's cost."""
+    say("case: LM 250000 curves, several per lane")
+    n = 250_000
+    Y, P, m = synth_curves(n, noise=0.0, seed=11)
+    r = np.random.default_rng(12)
+    kind = r.integers(0, 3, n)
+    Y[kind == 1] *= (1 + 0.05 * r.standard_normal((int((kind == 1).sum()), Y.shape[1]))).astype(np.float32)
+    Y[kind == 2] = (0.5 + 0.05 * r.standard_normal((int((kind == 2).sum()), Y.shape[1]))).astype(np.float32)
+    Yd = torch.from_numpy(Y).cuda()
+    pick = np.sort(r.choice(n, 2000, replace=False))
+    pick_d = torch.from_numpy(pick).cuda()
+    start = torch.from_numpy(np.stack([P[:, 0] * 0.8, P[:, 1] + 0.05, np.log(P[:, 2]) + 0.7], 1)
+                             .astype(np.float32)).cuda()
+    first = None
+    for init, fb in ((None, True), (start, True)):
+        big = gpu.fit(Yd, m, init=init, fallback=fb)
+        first = first or big
+        small = gpu.fit(Yd[pick_d].contiguous(), m, init=None if init is None else init[pick_d].contiguous(),
+                        fallback=fb)
+        torch.cuda.synchronize()
+        for a, b, what in zip(big, small, ("params", "iters", "flags")):
+            assert torch.equal(a[pick_d], b), (what, init is None)
+        fl = big[2].cpu().numpy()
+        say("init" if init is not None else "default", "converged %.4f, mean iters %.1f" %
+            (((fl & 1) != 0).mean(), big[1].float().mean().item()))
+    # the default-start fit of the noisy curves against the oracle's (clean ones fit to
+    # rounding, where a relative cost excess means nothing)
+    params, flags = first[0].cpu().numpy(), first[2].cpu().numpy()
+    sub = pick[kind[pick] == 1][:300]
+    Po, Co, Io, Fo = lm.lm_fit_many(Y[sub].astype(np.float64), m.astype(np.float64))
+    mm = m.astype(np.float64)
+    cost_g = np.array([np.sum((lm.model((p[0], p[1], np.log(p[2])), mm) - y) ** 2)
+                       for p, y in zip(params[sub].astype(np.float64), Y[sub].astype(np.float64))])
+    both = ((flags[sub] & 1) != 0) & ((Fo & 1) != 0)
+    say("both converged %.4f of %d" % (both.mean(), len(sub)))
+    assert both.mean() >= 0.9
+    excess = (cost_g[both] - Co[both]) / np.maximum(Co[both], 1e-30)
+    say("cost excess max %.3e" % excess.max())
+    assert excess.max() < 1e-4
