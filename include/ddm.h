@@ -411,8 +411,10 @@ ddm_status ddm_mlp_get_state(ddm_mlp_t mlp, float* params_host, float* adam_m_ho
 ddm_status ddm_mlp_set_state(ddm_mlp_t mlp, const float* params_host, const float* adam_m_host,
                              const float* adam_v_host, int64_t step);
 
-/* Inference: x_dev [rows][64] float32 -> y_dev [rows][3] float32 (any rows;
- * processed in chunks of max_batch).  Asynchronous. */
+/* Inference: x_dev [rows][64] float32 -> y_dev [rows][3] float32 (any rows).
+ * One launch over all rows whose workgroups keep 64 rows' activations in LDS
+ * (the same BF16 roundings, MFMA products and sums as the training forward,
+ * so the same results); uses no batch buffer.  Asynchronous. */
 ddm_status ddm_mlp_forward(ddm_mlp_t mlp, const float* x_dev, int64_t rows, float* y_dev);
 
 /* Forward + backward on one batch (1 <= B <= max_batch): keeps the gradient

@@ -186,6 +186,105 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
   pb[i] = to_bf16(pi);
 }
 
+// Inference of the whole network in one launch: a workgroup takes 64 rows,
+// keeps their activations in LDS (rounded to BF16 as the layered forward
+// rounds them between layers) and runs the four layers with k_gemm's MFMA
+// fragments, k order and epilogues, reading the weights from L2; only x and y
+// touch HBM.  The results are those of the layered forward.
+constexpr int kInfRows = 64;
+constexpr int kInfStride = DDM_MLP_HIDDEN + 8;  // LDS row stride (bf16): 528 bytes, rows 16-byte aligned
+
+__global__ void __launch_bounds__(256) k_mlp_infer(const float* __restrict__ x, int64_t rows,
+                                                   const __bf16* __restrict__ W1, const float* __restrict__ b1,
+                                                   const __bf16* __restrict__ W2, const float* __restrict__ b2,
+                                                   const __bf16* __restrict__ W3, const float* __restrict__ b3,
+                                                   const __bf16* __restrict__ W4, const float* __restrict__ b4,
+                                                   float* __restrict__ y) {
+  constexpr int NI = DDM_MLP_IN, NHd = DDM_MLP_HIDDEN, NO = DDM_MLP_OUT;
+  static_assert(NI % 16 == 0 && NHd == 4 * 64 && NO <= 32, "layer shapes of the fused inference");
+  __shared__ __bf16 Hs[kInfRows * kInfStride];
+  const int64_t r0 = (int64_t)blockIdx.x * kInfRows;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  {
+    // the input rows in BF16: thread t converts 16 consecutive inputs of row t / 4
+    const int r = threadIdx.x >> 2, c0 = (threadIdx.x & 3) * 16;
+    const int64_t gr = r0 + r;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) Hs[r * kInfStride + c0 + c] = to_bf16(gr < rows ? x[gr * NI + c0 + c] : 0.0f);
+  }
+  __syncthreads();
+  // hidden layers: wave w computes columns 64 w .. 64 w + 63 of all 64 rows
+  // (2 x 2 blocks of 32 x 32); a lane's A fragment is row (lane % 32),
+  // k = k0 + 8 (lane / 32) .. +7, its B fragment column (lane % 32) likewise
+  for (int l = 0; l < 3; ++l) {
+    const int K = l == 0 ? NI : NHd;
+    const __bf16* W = l == 0 ? W1 : (l == 1 ? W2 : W3);
+    const float* bias = l == 0 ? b1 : (l == 1 ? b2 : b3);
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[rb][cb][r] = 0.0f;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+        a[rb] = *reinterpret_cast<const bf16x8*>(&Hs[(32 * rb + (lane & 31)) * kInfStride + k0 + 8 * (lane >> 5)]);
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+        b[cb] = *reinterpret_cast<const bf16x8*>(W + (int64_t)(64 * wave + 32 * cb + (lane & 31)) * K + k0 +
+                                                 8 * (lane >> 5));
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
+    }
+    __syncthreads();  // every wave has read this layer's input
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        const int col = 64 * wave + 32 * cb + (lane & 31);
+        const float bc = bias[col];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = 32 * rb + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          Hs[row * kInfStride + col] = to_bf16(gelu_f(acc[rb][cb][r] + bc));
+        }
+      }
+    __syncthreads();
+  }
+  // output layer: waves 0 and 1 take 32 rows each, columns 0..31 with zero
+  // weights past the NO outputs (as k_gemm pads its B tile)
+  if (wave < 2) {
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    const int col = lane & 31;
+    for (int k0 = 0; k0 < NHd; k0 += 16) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&Hs[(32 * wave + (lane & 31)) * kInfStride + k0 + 8 * (lane >> 5)]);
+      bf16x8 b;
+      if (col < NO) {
+        b = *reinterpret_cast<const bf16x8*>(W4 + (int64_t)col * NHd + k0 + 8 * (lane >> 5));
+      } else {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) b[t] = (__bf16)0.0f;
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    if (col < NO) {
+      const float bc = b4[col];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t gr = r0 + 32 * wave + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (gr < rows) y[gr * NO + col] = acc[r] + bc;
+      }
+    }
+  }
+}
+
 // ---- launchers ----
 
 hipError_t launch_gemm(hipStream_t s, int epi, int M, int N, int K, const void* A, int64_t sam, int64_t sak,
@@ -244,6 +343,20 @@ hipError_t launch_adam(hipStream_t s, float* p, const float* g, float* m, float*
                        float b1, float b2, float eps, float bc1, float bc2) {
   hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m, v, (__bf16*)pb, n, lr, b1,
                      b2, eps, bc1, bc2);
+  return hipGetLastError();
+}
+
+// w[l], b[l]: the BF16 weights and FP32 biases of layer l (row-major
+// [out][in]); every weight pointer 16-byte aligned.
+hipError_t launch_mlp_infer(hipStream_t s, const float* x, int64_t rows, const void* const* w,
+                            const float* const* b, float* y) {
+  if (rows <= 0) return hipSuccess;
+  for (int l = 0; l < 4; ++l)
+    if (((uintptr_t)w[l] & 15) != 0) return hipErrorInvalidValue;
+  const int64_t grid = (rows + kInfRows - 1) / kInfRows;
+  if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)grid), dim3(256), 0, s, x, rows, (const __bf16*)w[0], b[0],
+                     (const __bf16*)w[1], b[1], (const __bf16*)w[2], b[2], (const __bf16*)w[3], b[3], y);
   return hipGetLastError();
 }
 

@@ -23,6 +23,8 @@ hipError_t launch_gemm(hipStream_t s, int epi, int M, int N, int K, const void* 
                        const void* B, int64_t sbk, int64_t sbn, const float* bias, float* C, int64_t ldc,
                        void* H, int64_t ldh, const float* Zin, int64_t ldz);
 hipError_t launch_to_bf16(hipStream_t s, const float* x, void* y, int64_t n);
+hipError_t launch_mlp_infer(hipStream_t s, const float* x, int64_t rows, const void* const* w,
+                            const float* const* b, float* y);
 hipError_t launch_mse(hipStream_t s, const float* Y, const float* T, int64_t n, void* dY, float* partial,
                       float* loss);
 hipError_t launch_colsum(hipStream_t s, const void* dZ, int64_t B, int N, float* db);
@@ -258,6 +260,18 @@ ddm_status ddm_mlp_forward(ddm_mlp_t n, const float* x, int64_t rows, float* y) 
   if (st != DDM_OK) return st;
   if (x == nullptr || y == nullptr) return api_fail(DDM_ERR_INVALID_ARGUMENT, "x/y is NULL");
   if (rows < 0) return api_fail(DDM_ERR_INVALID_ARGUMENT, "rows must be >= 0");
+  if (rows == 0) return DDM_OK;
+  // one fused launch over every row (activations kept in LDS) when the BF16
+  // weights allow its 16-byte loads, else the layers one by one in batches
+  const void* w[4] = {n->pb + OW1, n->pb + OW2, n->pb + OW3, n->pb + OW4};
+  const float* b[4] = {n->p + OB1, n->p + OB2, n->p + OB3, n->p + OB4};
+  bool aligned = true;
+  for (const void* wl : w) aligned = aligned && ((uintptr_t)wl & 15) == 0;
+  if (aligned) {
+    hipError_t e = launch_mlp_infer(n->stream, x, rows, w, b, y);
+    if (e != hipSuccess) return hipf(e, "mlp forward");
+    return DDM_OK;
+  }
   for (int64_t r0 = 0; r0 < rows; r0 += n->max_batch) {
     const int64_t B = std::min<int64_t>(n->max_batch, rows - r0);
     hipError_t e = launch_to_bf16(n->stream, x + r0 * NIN, n->xb, B * NIN);
