@@ -94,3 +94,24 @@ def test_training_lowers_loss(gpu):
     _, l1 = net.gradient(x[:1024], t[:1024])
     print("loss %.4e -> %.4e" % (l0, l1), flush=True)
     assert l1 < 0.1 * l0
+
+
+def test_inference_rows_are_independent(gpu):
+    """ddm_mlp_forward (one launch, 64 rows per workgroup): every row's output
+    is the same bits whatever the call's row count (1, 63, 64, 65, 1000 and
+    70,000 rows: partial and whole tiles, more rows than max_batch), and 1000
+    rows agree with the oracle at BF16 level."""
+    print("case: mlp inference row counts", flush=True)
+    net, theta, th_mix, X, T = setup(gpu, B=1000, seed=4)
+    r = np.random.default_rng(9)
+    Xl = torch.from_numpy(r.uniform(0, 1, (70_000, 64)).astype(np.float32)).cuda()
+    Xl[:1000] = torch.from_numpy(X).cuda()
+    Yl = net.forward(Xl)
+    for rows in (1, 63, 64, 65, 1000):
+        Y = net.forward(Xl[:rows].contiguous())
+        torch.cuda.synchronize()
+        assert torch.equal(Y, Yl[:rows]), rows
+    Yo, _ = om.forward(th_mix, om.bf16_round(X), round_hidden=True)
+    e = rel_fro(Yl[:1000].cpu().numpy(), Yo)
+    print("forward rel err %.3e" % e, flush=True)
+    assert e < 1e-2
