@@ -394,8 +394,9 @@ ddm_status ddm_fit(const ddm_fit_desc* desc, const float* curves_dev, const floa
 typedef struct ddm_mlp_s* ddm_mlp_t;
 
 /* Create a network with parameters uniform in +-1/sqrt(fan_in) from `seed`
- * and device buffers for batches of up to max_batch rows (about
- * max_batch * 5.6 KB plus 2.7 MB).  All work runs on `stream` (hipStream_t). */
+ * and device buffers for training batches of up to max_batch rows (about
+ * max_batch * 5.6 KB plus 2.7 MB; inference needs none of them).  All work
+ * runs on `stream` (hipStream_t). */
 ddm_status ddm_mlp_create(uint64_t seed, int64_t max_batch, void* stream, ddm_mlp_t* out);
 ddm_status ddm_mlp_destroy(ddm_mlp_t mlp);
 

@@ -114,8 +114,9 @@ class Initialiser:
         s = std.detach().cpu().numpy().astype(np.float64)
         p[_OW4:_OB4] = (p[_OW4:_OB4].reshape(3, 256) * s[:, None]).ravel()
         p[_OB4:_OB4 + 3] = p[_OB4:_OB4 + 3] * s + m
-        # inference runs over whole stacks: large batches, few launches
-        self.net = api.Mlp(seed=0, max_batch=max(net.max_batch, 1 << 17), device=net.device)
+        # inference over a whole stack is one launch whatever max_batch is (it
+        # sizes only the training buffers)
+        self.net = api.Mlp(seed=0, max_batch=net.max_batch, device=net.device)
         self.net.set_params(p.astype(np.float32))
 
     def init(self, curves):
