@@ -684,9 +684,9 @@ def direct_leg(frames, pixel, reps=3):
 
 
 def long_stack_leg(recipe, M, N=16384, steps=3):
-    """The bench frames' recipe at N = 16384 frames (the paper's longest stacks),
-    beyond the time transform's lengths: step one, then step two by direct
-    differences for M lags, timed over whole steps (the frames resident in HBM)."""
+    """The bench frames' recipe at N = 16384 frames (the paper's longest stacks):
+    step one, then step two by direct differences for M lags, timed over whole
+    steps (the frames resident in HBM); then all N lags by both methods."""
     import torch
     from paper_2012_05695_amd import api, synth
     W, H = recipe["W"], recipe["H"]
@@ -708,11 +708,54 @@ def long_stack_leg(recipe, M, N=16384, steps=3):
     per = {("direct" if k == "time" else k): v[0] / steps for k, v in prof.items() if v[1] > 0}
     nq = plan.n_q
     plan.close()
-    del frames, D
+    del D
     torch.cuda.empty_cache()
-    return {"workload": "%dx%d %s x %d frames, %d lags, step two by direct differences" % (W, H, recipe["pixel"], N, M),
-            "ms_per_stack": ms, "frames_per_s": N / (ms * 1e-3), "kernel_ms": per,
-            "algorithmic_bytes": N * H * W * (2 if recipe["pixel"] == "u16" else 1) + 2 * nq * N * 8 + nq * M * 4}
+    out = {"workload": "%dx%d %s x %d frames, %d lags, step two by direct differences" % (W, H, recipe["pixel"], N, M),
+           "ms_per_stack": ms, "frames_per_s": N / (ms * 1e-3), "kernel_ms": per,
+           "algorithmic_bytes": N * H * W * (2 if recipe["pixel"] == "u16" else 1) + 2 * nq * N * 8 + nq * M * 4}
+    out["all_lags"] = long_stack_all_lags(recipe, frames, N)
+    del frames
+    torch.cuda.empty_cache()
+    return out
+
+
+def long_stack_all_lags(recipe, frames, N, steps=3):
+    """All N lags of the same stack by the time transform of length 16384 and,
+    once, by direct differences (the comparison the paper draws between the two
+    schemes at its longest stacks); the largest per-q relative difference of
+    the two D."""
+    import torch
+    from paper_2012_05695_amd import api
+    W, H = recipe["W"], recipe["H"]
+    res, Ds = {}, {}
+    for method, reps in (("fourier", steps), ("direct", 1)):
+        print("bench: long stack, all %d lags, %s" % (N, method), file=sys.stderr, flush=True)
+        plan = api.Plan(W, H, N, pixel=recipe["pixel"], method=method)
+        plan.allocate_workspace()
+        D = plan.structure_function(frames)
+        torch.cuda.synchronize()
+        plan.set_profiling(["step1", "row", "col", "time"])
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            plan.structure_function(frames, out=D)
+        ev[1].record()
+        torch.cuda.synchronize()
+        plan.status()
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        prof = {k: plan.profile(k) for k in ("step1", "row", "col", "time")}
+        name = "time" if method == "fourier" else "direct"
+        per = {(name if k == "time" else k): v[0] / reps for k, v in prof.items() if v[1] > 0}
+        res[method] = {"ms_per_stack": ms, "frames_per_s": N / (ms * 1e-3), "kernel_ms": per}
+        plan.close()
+        Ds[method] = D
+    num = (Ds["fourier"].double() - Ds["direct"].double()).abs().amax(dim=1)
+    den = Ds["direct"].double().amax(dim=1).clamp_min(1e-300)
+    res["max_rel_diff_fourier_vs_direct"] = float((num / den).max())
+    res["direct_over_fourier"] = res["direct"]["ms_per_stack"] / res["fourier"]["ms_per_stack"]
+    del Ds, D
+    torch.cuda.empty_cache()
+    return res
 
 
 def finish(args, out, frames_cpu, nq):

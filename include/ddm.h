@@ -76,14 +76,14 @@ typedef enum ddm_padding { DDM_PAD_POW2 = 0, DDM_PAD_MINIMAL = 1 } ddm_padding;
 
 /* How step two computes D from the image spectra.
  * FOURIER: the time transform of Appendix B (Eq. (B3), (B4)): O(N log N) per
- *   wave vector, whatever max_lag is.
+ *   wave vector, whatever max_lag is; N up to 16384 (N2 up to 32768).
  * DIRECT: Eq. (1) term by term, |F_{n+m}(q) - F_n(q)|^2 averaged over the
  *   N - m pairs of each lag (the direct scheme of section "The algorithm",
  *   applied to the stored spectra: the spectrum of a difference image is the
  *   difference of the spectra): O(N M) per wave vector.  FP32 differences,
  *   FP32 sums over 64 time points added into FP64 totals.  Cheaper than
  *   FOURIER when few lags are wanted (at 512 x 512 x 1024 below about 52); the
- *   only method for N above 8192 (up to 65536).
+ *   only method for N above 16384 (up to 65536).
  * AUTO: DIRECT where a cost model (N M - M (M - 1) / 2 difference pairs
  *   against 5.2 L log2 L for the transform of length L, the constant from the
  *   measured crossover) expects it to be faster, else FOURIER;
@@ -97,7 +97,7 @@ typedef struct ddm_plan_desc {
   uint32_t struct_size;  /* = sizeof(ddm_plan_desc); guards ABI drift */
   int32_t width;         /* W: even, 8..4096, a power of two or 3 * a power of two */
   int32_t height;        /* H: same rules as W */
-  int32_t n_frames;      /* N >= 2 (up to 8192: time FFT length N2 <= 16384; up to
+  int32_t n_frames;      /* N >= 2 (up to 16384: time FFT length N2 <= 32768; up to
                             65536 with DDM_METHOD_DIRECT) */
   int32_t max_lag;       /* M in [1, N]: lags 0..M-1 are produced; 0 means N */
   int32_t pixel;         /* ddm_pixel of the frames */

@@ -270,8 +270,8 @@ static ddm_status check_desc(const ddm_plan_desc* desc) {
   if (desc->method != DDM_METHOD_FOURIER && desc->method != DDM_METHOD_DIRECT && desc->method != DDM_METHOD_AUTO)
     return fail(DDM_ERR_INVALID_ARGUMENT, "method must be DDM_METHOD_FOURIER, _DIRECT or _AUTO");
   if (N > 65536) return fail(DDM_ERR_UNSUPPORTED, "n_frames > 65536");
-  if (N > 8192 && desc->method == DDM_METHOD_FOURIER)
-    return fail(DDM_ERR_UNSUPPORTED, "n_frames > 8192 (time FFT length > 16384) needs DDM_METHOD_DIRECT");
+  if (N > 16384 && desc->method == DDM_METHOD_FOURIER)
+    return fail(DDM_ERR_UNSUPPORTED, "n_frames > 16384 (time FFT length > 32768) needs DDM_METHOD_DIRECT");
   if (desc->max_lag < 0 || desc->max_lag > N)
     return fail(DDM_ERR_INVALID_ARGUMENT, "max_lag must be in [0, n_frames]");
   if (desc->pixel != DDM_PIX_U8 && desc->pixel != DDM_PIX_U16)
@@ -306,7 +306,7 @@ ddm_status ddm_plan_create(const ddm_plan_desc* desc, ddm_plan_t* out) {
   while (l < N) l <<= 1;
   p->n2_paper = 2 * l;
   p->L = time_length(N, desc->padding);
-  p->method = desc->method == DDM_METHOD_AUTO ? (N > 8192 || direct_cheaper(N, p->M, p->L) ? DDM_METHOD_DIRECT
+  p->method = desc->method == DDM_METHOD_AUTO ? (N > 16384 || direct_cheaper(N, p->M, p->L) ? DDM_METHOD_DIRECT
                                                                                          : DDM_METHOD_FOURIER)
                                               : desc->method;
   const int64_t g = std::gcd(W, H);

@@ -35,7 +35,7 @@ int main() {
       {[](ddm_plan_desc& x) { x.width = 100; x.height = 64; x.n_frames = 8; }, UNS, "width 100"},
       {[](ddm_plan_desc& x) { x.width = 64; x.height = 8192; x.n_frames = 8; }, UNS, "height 8192"},
       {[](ddm_plan_desc& x) { x.width = 64; x.height = 64; x.n_frames = 1; }, INV, "n_frames 1"},
-      {[](ddm_plan_desc& x) { x.width = 64; x.height = 64; x.n_frames = 9000; }, UNS, "n_frames 9000 fourier"},
+      {[](ddm_plan_desc& x) { x.width = 64; x.height = 64; x.n_frames = 17000; }, UNS, "n_frames 17000 fourier"},
       {[](ddm_plan_desc& x) { x.width = 64; x.height = 64; x.n_frames = 70000; x.method = DDM_METHOD_DIRECT; },
        UNS, "n_frames 70000 direct"},
       {[](ddm_plan_desc& x) { x.width = 64; x.height = 64; x.n_frames = 8; x.max_lag = 9; }, INV, "max_lag > N"},

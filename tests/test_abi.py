@@ -93,7 +93,7 @@ def test_host_only_calls(libddm_path):
     d.method = 3
     assert lib.ddm_plan_create(ctypes.byref(d), ctypes.byref(h)) == _lib.DDM_ERR_INVALID_ARGUMENT
     assert b"method" in lib.ddm_last_error()
-    d.method, d.n_frames = _lib.DDM_METHOD_FOURIER, 8193
+    d.method, d.n_frames = _lib.DDM_METHOD_FOURIER, 16385
     assert lib.ddm_plan_create(ctypes.byref(d), ctypes.byref(h)) == _lib.DDM_ERR_UNSUPPORTED
     assert b"DDM_METHOD_DIRECT" in lib.ddm_last_error()
     d.method, d.n_frames = _lib.DDM_METHOD_DIRECT, 65537

@@ -1,0 +1,83 @@
+"""Step two by the Fourier route at the time-transform length L = 16384
+(8192 < N <= 16384, N2 = 32768 in Eq. (B4)).
+
+Each case is compared with the oracle (FP64 direct differences, Eq. (1), of a
+naive DFT) on every ky and every lag of a subset of kx columns:
+  * N = L = 16384, all lags (the 16 largest lags summed directly);
+  * N = 12000 with max_lag 6000 (a zero-padded tail, truncated output);
+  * the FP16 per-q-scaled store at N = 9000;
+  * the plain [q][N] layout (the step-two-only call) at N = 9000 and 16384.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import structure
+from paper_2012_05695_amd import synth
+
+from helpers import TOL_F32, describe, oracle_D, per_q_error
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def check_sampled(D_dev, frames_dev, cols, label, max_lag=None, tol=TOL_F32):
+    Dg = D_dev.cpu().numpy()
+    Do, rows = oracle_D(frames_dev.cpu().numpy(), kx_subset=cols, max_lag=max_lag)
+    e = per_q_error(Dg[rows], Do)
+    say(label, "(%d q):" % len(rows), describe(e))
+    assert e.max() <= tol
+    assert np.all(Dg[:, 0] == 0.0)
+    assert np.all(np.isfinite(Dg))
+
+
+def test_fourier_64x64x16384(gpu):
+    say("case: fourier 64x64x16384 u16 (N = L), kx columns {0, 5, 32}")
+    frames = synth.brownian_stack(64, 64, 16384, 40, 1.5, 40.0, 800.0, 0.1, seed=16385, pixel="u16", device="cuda")
+    plan = gpu.Plan(64, 64, 16384)
+    assert plan.method == "fourier"
+    D = plan.structure_function(frames)
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    check_sampled(D, frames, [0, 5, 32], "64x64x16384 fourier")
+
+
+def test_fourier_32x32x12000_truncated(gpu):
+    say("case: fourier 32x32x12000 u8, max_lag 6000, kx columns {0, 7, 16}")
+    frames = synth.brownian_stack(32, 32, 12000, 12, 1.5, 40.0, 200.0, 0.3, seed=12000, pixel="u8", device="cuda")
+    plan = gpu.Plan(32, 32, 12000, pixel="u8", max_lag=6000, method="fourier")
+    D = plan.structure_function(frames)
+    torch.cuda.synchronize()
+    assert D.shape[1] == 6000
+    check_sampled(D, frames, [0, 7, 16], "32x32x12000 fourier, 6000 lags", max_lag=6000)
+
+
+def test_fourier_f16_32x32x9000(gpu):
+    say("case: fourier 32x32x9000 u16, FP16 store, kx columns {0, 3}")
+    frames = synth.brownian_stack(32, 32, 9000, 12, 1.5, 40.0, 400.0, 0.3, seed=9001, pixel="u16", device="cuda")
+    plan = gpu.Plan(32, 32, 9000, spectrum="f16", method="fourier")
+    D = plan.structure_function(frames)
+    torch.cuda.synchronize()
+    check_sampled(D, frames, [0, 3], "32x32x9000 fourier FP16 store", tol=5e-3)
+
+
+@pytest.mark.parametrize("N", [9000, 16384])
+def test_fourier_plain_layout(gpu, N):
+    say("case: step two from [q][N] spectra, N =", N)
+    r = np.random.default_rng(N)
+    plan = gpu.Plan(16, 16, N, k2_max=12, method="fourier")
+    nq = plan.n_q
+    F = (r.standard_normal((nq, N)) + 1j * r.standard_normal((nq, N))).astype(np.complex64)
+    F += np.complex64(20 + 5j)  # a static offset per q
+    Dg = plan.structure_from_spectra(torch.from_numpy(F).cuda()).cpu().numpy()
+    Do = structure.structure_function_direct(F.astype(np.complex128))
+    e = per_q_error(Dg, Do)
+    say("N", N, "(%d q)" % nq, describe(e))
+    assert e.max() <= TOL_F32
