@@ -60,6 +60,9 @@ def parse():
                     help="run only this many steps and nothing else (for profilers)")
     ap.add_argument("--f16", action="store_true",
                     help="with --kernel-only: the FP16 per-q-scaled spectra store (profiles; never a bench line)")
+    ap.add_argument("--frames", type=int, default=0,
+                    help="with --kernel-only: this many frames of the workload's recipe (profiles of "
+                         "the long-stack kernels; never a bench line)")
     ap.add_argument("--direct-lags", type=int, default=0,
                     help="with --kernel-only: step two by direct differences for this many lags "
                          "(profiles of the direct kernel; never a bench line)")
@@ -416,8 +419,8 @@ def batched_leg(n_stacks, log, lanes=4):
 
 def main():
     args = parse()
-    if (args.direct_lags or args.f16) and args.kernel_only is None:
-        print("bench.py: --direct-lags and --f16 are for --kernel-only profiling runs", file=sys.stderr)
+    if (args.direct_lags or args.f16 or args.frames) and args.kernel_only is None:
+        print("bench.py: --direct-lags, --f16 and --frames are for --kernel-only profiling runs", file=sys.stderr)
         sys.exit(2)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the path shards over q across GPUs "
@@ -436,10 +439,10 @@ def main():
         return
 
     recipe = {"paper": synth.PAPER, "plain": synth.PLAIN, "large": synth.LARGE}[args.config]
-    W, H, N = recipe["W"], recipe["H"], recipe["N"]
+    W, H, N = recipe["W"], recipe["H"], args.frames or recipe["N"]
     print("bench: generating %dx%dx%d %s stack on GPU" % (W, H, N, recipe["pixel"]), file=sys.stderr,
           flush=True)
-    frames = synth.make(recipe, device="cuda")
+    frames = synth.make(recipe, device="cuda", N=N)
     torch.cuda.synchronize()
     spectrum = "f16" if args.f16 else "f32"
     if args.direct_lags:

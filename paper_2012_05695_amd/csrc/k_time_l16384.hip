@@ -40,6 +40,23 @@ __device__ __forceinline__ int opaque(int t) {
   return t;
 }
 
+// The FFT passes of length kLongL, their twiddles w_L^j = e^{-2 pi i j / L}
+// taken as th[j >> 7] * tl[j & 127] from two 128-entry LDS tables (th[h] =
+// w_L^{128 h}, tl[l] = w_L^l) instead of scattered reads of the global table.
+template <int NS>
+struct LongPasses {
+  static constexpr int R = pick_radix(kLongL / NS, kLongE);
+  __device__ __forceinline__ static void run(float2 (&v)[kLongE], LdsView<1, true> buf, int tid,
+                                             const float2* th, const float2* tl) {
+    stockham_pass_g<kLongL, kLongE, R, NS, 1, true, false>(v, buf, tid, [&](int, int k, int jm) {
+      const int j = k * jm * (kLongL / (NS * R));
+      return cmul(th[j >> 7], tl[j & 127]);
+    });
+    if constexpr (NS * R < kLongL) LongPasses<NS * R>::run(v, buf, tid, th, tl);
+  }
+};
+static_assert(kLongL == 128 * 128, "two-level twiddle tables of 128 entries");
+
 template <int QB, bool F16>
 __global__ void __launch_bounds__(kLongT) k_time_long(const void* __restrict__ spec, int64_t nq, int N, int M,
                                                     const float2* __restrict__ twN2,
@@ -55,6 +72,7 @@ __global__ void __launch_bounds__(kLongT) k_time_long(const void* __restrict__ s
   __shared__ double wtot4[4];
   __shared__ float redf[T / 64];
   __shared__ float2 ends[2 * kTailLags];  // x'_n for n < kTailLags and N - kTailLags <= n < N
+  __shared__ float2 th[128], tl[128];     // two-level twiddle tables (LongPasses)
 
   // uniform per workgroup: a padding id or a slot without a row of D
   const int64_t q0 = time_q0<1, QB>(blockIdx.x);
@@ -64,6 +82,10 @@ __global__ void __launch_bounds__(kLongT) k_time_long(const void* __restrict__ s
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   LdsView<1, true> yb{buf};
+  if (tid < 128) {  // twN2[2 j] = w_L^j; read before the first transform (group_sum synchronises)
+    th[tid] = twN2[2 * 128 * tid];
+    tl[tid] = twN2[2 * tid];
+  }
 
   // ---- load x_n, n = tid + e T (zero for n >= N: reads past the range return 0) ----
   __amdgpu_buffer_rsrc_t in_r;
@@ -124,7 +146,7 @@ __global__ void __launch_bounds__(kLongT) k_time_long(const void* __restrict__ s
   }
 
   // ---- X_even = FFT_L(x'), X_odd = FFT_L(x' w^n); z = IFFT_L(P_even + i P_odd) ----
-  fft_forward<L, E, 1, true, false>(v, yb, opaque(tid), opaque(twN2), 2);
+  LongPasses<1>::run(v, yb, opaque(tid), th, tl);
   float pe[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) pe[e] = v[e].x * v[e].x + v[e].y * v[e].y;
@@ -135,10 +157,14 @@ __global__ void __launch_bounds__(kLongT) k_time_long(const void* __restrict__ s
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = cmul(v[e], tw[tid + e * T]);
   }
-  fft_forward<L, E, 1, true, false>(v, yb, opaque(tid), opaque(twN2), 2);
+  LongPasses<1>::run(v, yb, opaque(tid), th, tl);
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = make_float2(pe[e], v[e].x * v[e].x + v[e].y * v[e].y);
-  fft_inverse<L, E, 1, true, false>(v, yb, opaque(tid), opaque(twN2), 2);
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = cconj(v[e]);  // inverse by conjugation
+  LongPasses<1>::run(v, yb, opaque(tid), th, tl);
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = cconj(v[e]);
 #pragma unroll
   for (int e = 0; e < E; ++e) yb[tid + e * T] = v[e];
   __syncthreads();
