@@ -85,8 +85,9 @@ typedef enum ddm_padding { DDM_PAD_POW2 = 0, DDM_PAD_MINIMAL = 1 } ddm_padding;
  *   FOURIER when few lags are wanted (at 512 x 512 x 1024 below about 52); the
  *   only method for N above 16384 (up to 65536).
  * AUTO: DIRECT where a cost model (N M - M (M - 1) / 2 difference pairs
- *   against 5.2 L log2 L for the transform of length L, the constant from the
- *   measured crossover) expects it to be faster, else FOURIER;
+ *   against c L log2 L for the transform of length L, c = 5.2 up to L = 8192
+ *   and 16 at L = 16384, the constants from the measured crossovers) expects
+ *   it to be faster, else FOURIER;
  *   ddm_plan_autotune replaces the model's choice by a timing of both.
  *   ddm_plan_method reports the choice. */
 typedef enum ddm_method { DDM_METHOD_FOURIER = 0, DDM_METHOD_DIRECT = 1, DDM_METHOD_AUTO = 2 } ddm_method;

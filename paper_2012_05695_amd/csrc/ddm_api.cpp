@@ -87,9 +87,13 @@ constexpr int kReadback = 4;                      // calls in flight before the 
 // faster at 56 for both N = 512 and N = 1024 (at 256 x 256, with fewer wave
 // vectors, direct stays faster to about 80 lags at N = 2048 and 96 at 4096;
 // the model keeps the larger frames' constant there, and autotune times both).
+// The length-16384 kernel (one wave vector per workgroup) costs relatively
+// more: at 512 x 512 x 16384 direct is faster at 192 lags and the transform at
+// 256 (crossover near 224 lags), hence the constant 16 there.
 bool direct_cheaper(int N, int M, int L) {
   const double pairs = (double)N * M - 0.5 * (double)M * (M - 1);
-  return pairs < 5.2 * L * std::log2((double)L);
+  const double c = L >= 16384 ? 16.0 : 5.2;
+  return pairs < c * L * std::log2((double)L);
 }
 
 }  // namespace
@@ -1279,7 +1283,7 @@ ddm_status ddm_plan_autotune(ddm_plan_t p, int32_t* E_out, int32_t* qpw_out, dou
   if (p->ws == nullptr) return fail(DDM_ERR_OUT_OF_MEMORY, "autotune needs the workspace (ddm_plan_set_workspace)");
   const char* env = std::getenv("DDM_AUTOTUNE");
   const bool off = env && std::strcmp(env, "off") == 0;
-  const bool want_fourier = p->d.method != DDM_METHOD_DIRECT && p->N <= 8192;
+  const bool want_fourier = p->d.method != DDM_METHOD_DIRECT && p->N <= 16384;
   const bool want_direct = p->d.method != DDM_METHOD_FOURIER;
   const auto key = std::make_tuple(p->L, p->N, p->M, (int)p->f16);
   double best_ms = -1.0, direct_ms = -1.0;
@@ -1336,7 +1340,15 @@ ddm_status ddm_plan_autotune(ddm_plan_t p, int32_t* E_out, int32_t* qpw_out, dou
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
       *ms_all = ms / 2.0 * ((double)p->nslots / (double)nq_t);
     };
-    if (!have) {
+    if (!have && p->L == 16384) {
+      // the length-16384 kernel has one launch shape (16 values per thread,
+      // one wave vector per workgroup): timed for the method choice only
+      const TimeShape sh{16, 1};
+      time_it([&] {
+        return launch_time(p->stream, p->L, spec, kSpecQB, nq_t, p->N, p->M, p->twT, p->ramp, nullptr, qexp, dout, sh);
+      }, &best_ms);
+      best = sh;
+    } else if (!have) {
       for (int E : {16, 8, 12}) {
         for (int qpw : {1, 2, 4, 8, 16}) {
           if (e != hipSuccess) break;

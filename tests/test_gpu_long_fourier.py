@@ -81,3 +81,21 @@ def test_fourier_plain_layout(gpu, N):
     e = per_q_error(Dg, Do)
     say("N", N, "(%d q)" % nq, describe(e))
     assert e.max() <= TOL_F32
+
+
+def test_method_choice_at_16384(gpu):
+    """DDM_METHOD_AUTO at N = 16384: the cost model takes direct differences
+    below the measured crossover (about 224 lags at 512x512) and the transform
+    above it; ddm_plan_autotune times both and reports the length-16384
+    kernel's single launch shape."""
+    say("case: method choice at N = 16384")
+    for M, want in ((192, "direct"), (256, "fourier")):
+        plan = gpu.Plan(64, 64, 16384, max_lag=M, method="auto")
+        assert plan.method == want, (M, plan.method)
+        plan.close()
+    plan = gpu.Plan(64, 64, 16384, max_lag=192, method="auto")
+    E, qpw, ms = plan.autotune()
+    say("autotune 64x64x16384, 192 lags:", plan.method, E, qpw, "%.3f ms" % ms)
+    assert (E, qpw) == (16, 1) and ms > 0
+    assert plan.method in ("direct", "fourier")
+    plan.close()
