@@ -6,7 +6,8 @@ naive DFT) on every ky and every lag of a subset of kx columns:
   * N = L = 16384, all lags (the 16 largest lags summed directly);
   * N = 12000 with max_lag 6000 (a zero-padded tail, truncated output);
   * the FP16 per-q-scaled store at N = 9000;
-  * the plain [q][N] layout (the step-two-only call) at N = 9000 and 16384.
+  * the plain [q][N] layout (the step-two-only call) at N = 8193, 9000 and 16384;
+  * the same D bit for bit on a second call (fixed-order sums, no atomics).
 """
 
 import sys
@@ -46,6 +47,9 @@ def test_fourier_64x64x16384(gpu):
     D = plan.structure_function(frames)
     torch.cuda.synchronize()
     assert plan.status() == 0
+    D2 = plan.structure_function(frames)
+    torch.cuda.synchronize()
+    assert torch.equal(D, D2)
     check_sampled(D, frames, [0, 5, 32], "64x64x16384 fourier")
 
 
@@ -68,7 +72,7 @@ def test_fourier_f16_32x32x9000(gpu):
     check_sampled(D, frames, [0, 3], "32x32x9000 fourier FP16 store", tol=5e-3)
 
 
-@pytest.mark.parametrize("N", [9000, 16384])
+@pytest.mark.parametrize("N", [8193, 9000, 16384])
 def test_fourier_plain_layout(gpu, N):
     say("case: step two from [q][N] spectra, N =", N)
     r = np.random.default_rng(N)
