@@ -10,7 +10,7 @@
 // Layout for this length: one wave vector per workgroup of 1024 threads, 16
 // values per thread held in registers.  LDS holds a single L-element buffer
 // (136 KB with padding) that serves, in turn, every FFT pass's exchange, the
-// inverse's mirrored reads and the prefix sums (as doubles), instead of a
+// inverse's mirrored reads, then 2 Re c(m) and the prefix sums, instead of a
 // staged sequence plus an exchange buffer (which would need 272 KB); the
 // sequence is read three times instead (for each forward transform and for
 // the prefix sums), the re-reads from lines that the L2 still holds.
@@ -170,29 +170,35 @@ __global__ void __launch_bounds__(kLongT) k_time_long(const void* __restrict__ s
   __syncthreads();
 
   // ---- 2 Re c(m) = (2/N2) Re sum_k P_k e^{2 pi i k m / N2} for m = tid + e T,
-  // from z_m and z_{L-m}; parked in the output row, element m, which only this
-  // thread writes and reads (held in registers through the prefix sums, these
-  // values would not fit) ----
+  // from z_m and z_{L-m}; kept in the first quarter of the buffer (as floats,
+  // element m) once every z has been read ----
   const float inv_l = 1.0f / (float)L;  // 2 / N2
-  float* drow = D + (size_t)qd * M;
-  const float2* tw = opaque(twN2);
+  float* tcl = reinterpret_cast<float*>(buf);      // 2 Re c(m), m < L
+  float* sl = reinterpret_cast<float*>(buf) + L;   // wave-local parts of S(n), n < L
+  {
+    const float2* tw = opaque(twN2);
+    float two_c[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int m = tid + e * T;
-    const float2 zm = v[e];
-    const float2 zr = yb[m == 0 ? 0 : L - m];
-    const float2 w = tw[m];  // (cos th, -sin th), th = 2 pi m / N2
-    if (m < M) drow[m] = 0.5f * ((zm.x + zr.x) + w.x * (zm.y + zr.y) - w.y * (zm.x - zr.x)) * inv_l;
+    for (int e = 0; e < E; ++e) {
+      const int m = tid + e * T;
+      const float2 zm = v[e];
+      const float2 zr = yb[m == 0 ? 0 : L - m];
+      const float2 w = tw[m];  // (cos th, -sin th), th = 2 pi m / N2
+      two_c[e] = 0.5f * ((zm.x + zr.x) + w.x * (zm.y + zr.y) - w.y * (zm.x - zr.x)) * inv_l;
+    }
+    __syncthreads();  // every z has been read: the buffer holds 2 Re c and S from here on
+#pragma unroll
+    for (int e = 0; e < E; ++e) tcl[tid + e * T] = two_c[e];
   }
-  __syncthreads();  // the buffer holds the prefix sums from here on
 
-  // ---- prefix sums S(n) = sum_{j<n} |x'_j|^2 in FP64 for n = tid + e T: a wave
-  // scan per chunk e (kept in the buffer as doubles), then the exclusive scan of
-  // the (chunk, wave) totals in n order; S(n) = wave part + offset of its
-  // (chunk, wave) ----
+  // ---- prefix sums S(n) = sum_{j<n} |x'_j|^2 for n = tid + e T: a wave scan in
+  // FP64 per chunk e, whose exclusive part (a sum of at most 63 terms) is kept
+  // as a float in the buffer, then the FP64 exclusive scan of the (chunk, wave)
+  // totals in n order; S(n) = wave part + offset of its (chunk, wave).  The
+  // float rounding of the wave part (a relative 2^-24 of at most 63 |x'|^2) is
+  // far below the FP32 transform route's error in 2 Re c(m). ----
   load_x(v);
   offset_free(v);
-  double* sd = reinterpret_cast<double*>(buf);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const double d = (double)v[e].x * v[e].x + (double)v[e].y * v[e].y;
@@ -203,7 +209,7 @@ __global__ void __launch_bounds__(kLongT) k_time_long(const void* __restrict__ s
       if (lane >= o) incl += y;
     }
     const double excl = __shfl_up(incl, 1, 64);
-    sd[tid + e * T] = (lane == 0) ? 0.0 : excl;
+    sl[tid + e * T] = (lane == 0) ? 0.0f : (float)excl;
     if (lane == 63) wtot[e * (T / 64) + wave] = incl;
   }
   __syncthreads();
@@ -231,9 +237,10 @@ __global__ void __launch_bounds__(kLongT) k_time_long(const void* __restrict__ s
   const double sN = ((wtot4[0] + wtot4[1]) + wtot4[2]) + wtot4[3];  // S(N)
   __syncthreads();
   // S(n), 0 <= n < L (S(n) = S(N) for n >= N)
-  auto S = [&](int n) { return sd[n] + wtot[(n / T) * (T / 64) + (n % T) / 64]; };
+  auto S = [&](int n) { return (double)sl[n] + wtot[(n / T) * (T / 64) + (n % T) / 64]; };
 
   // ---- D(m) = (S(N-m) + S(N) - S(m) - 2 Re c(m)) / (N - m); D(q, 0) = 0 ----
+  float* drow = D + (size_t)qd * M;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int m = tid + e * T;
@@ -242,7 +249,7 @@ __global__ void __launch_bounds__(kLongT) k_time_long(const void* __restrict__ s
         drow[0] = 0.0f;  // lag 0 pairs every frame with itself
         continue;
       }
-      double sum = (S(N - m) + sN) - S(m) - (double)drow[m];
+      double sum = (S(N - m) + sN) - S(m) - (double)tcl[m];
       if (m >= N - kTailLags) {
         // fewer than kTailLags pairs: Eq. (1) summed directly, in order
         float acc = 0.0f;
