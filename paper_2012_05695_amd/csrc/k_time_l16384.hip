@@ -4,8 +4,9 @@
 // Eq. (B4)).  The arithmetic is that of k_time (time_kernel.hpp): per-q mean
 // removal, the N2-point forward FFT of the half-zero sequence as two L-point
 // FFTs (X_2j = FFT_L(x)_j, X_2j+1 = FFT_L(x_n w^n)_j, w = e^{-2 pi i / N2}), one
-// packed L-point inverse of the power spectrum, FP64 prefix sums and an FP64
-// combination, the kTailLags largest lags summed from Eq. (1) directly.
+// packed L-point inverse of the power spectrum, prefix sums with FP64 offsets
+// (wave-local parts rounded to floats) and an FP64 combination, the kTailLags
+// largest lags summed from Eq. (1) directly.
 //
 // Layout for this length: one wave vector per workgroup of 1024 threads, 16
 // values per thread held in registers.  LDS holds a single L-element buffer
