@@ -7,7 +7,8 @@ naive DFT) on every ky and every lag of a subset of kx columns:
   * N = 12000 with max_lag 6000 (a zero-padded tail, truncated output);
   * the FP16 per-q-scaled store at N = 9000;
   * the plain [q][N] layout (the step-two-only call) at N = 8193, 9000 and 16384;
-  * the same D bit for bit on a second call (fixed-order sums, no atomics).
+  * the same D bit for bit on a second call (fixed-order sums, no atomics);
+  * a batch (captured graph) holding such a stack, bit-identical to single plans.
 """
 
 import sys
@@ -103,3 +104,24 @@ def test_method_choice_at_16384(gpu):
     assert (E, qpw) == (16, 1) and ms > 0
     assert plan.method in ("direct", "fourier")
     plan.close()
+
+
+def test_batch_with_long_stack(gpu):
+    """A batch (one captured graph over two lanes) holding a stack on the
+    length-16384 transform: D bit-identical to single plans, on the first
+    capture and on a replay."""
+    say("case: batch of 32x32x9000 and 64x64x300 on two lanes")
+    shapes = [(32, 32, 9000), (64, 64, 300)]
+    fr = [synth.brownian_stack(W, H, N, 12, 1.5, 40.0, 400.0, 0.2, seed=9100 + i, pixel="u16", device="cuda")
+          for i, (W, H, N) in enumerate(shapes)]
+    batch = gpu.Batch(shapes, lanes=2)
+    Db = [d.clone() for d in batch.structure_function(fr)]
+    Db2 = batch.structure_function(fr)  # graph replay
+    torch.cuda.synchronize()
+    for i, (W, H, N) in enumerate(shapes):
+        plan = gpu.Plan(W, H, N)
+        Ds = plan.structure_function(fr[i])
+        torch.cuda.synchronize()
+        assert torch.equal(Db[i], Ds), i
+        assert torch.equal(Db2[i], Ds), i
+        plan.close()
