@@ -8,7 +8,9 @@ naive DFT) on every ky and every lag of a subset of kx columns:
   * the FP16 per-q-scaled store at N = 9000;
   * the plain [q][N] layout (the step-two-only call) at N = 8193, 9000 and 16384;
   * the same D bit for bit on a second call (fixed-order sums, no atomics);
-  * a batch (captured graph) holding such a stack, bit-identical to single plans.
+  * a batch (captured graph) holding such a stack, bit-identical to single plans;
+  * holes of a low-q cut in the blocked store, with the minimum workspace
+    (several groups of wave vectors).
 """
 
 import sys
@@ -125,3 +127,22 @@ def test_batch_with_long_stack(gpu):
         assert torch.equal(Db[i], Ds), i
         assert torch.equal(Db2[i], Ds), i
         plan.close()
+
+
+def test_fourier_long_holes_and_groups(gpu):
+    """Length-16384 transform on the blocked store with holes (a low-q cut)
+    and the minimum workspace (several groups of wave vectors, every frame
+    transformed per group); every q against the oracle."""
+    say("case: fourier 32x32x9000 u8, k2_max 60, minimum workspace")
+    frames = synth.brownian_stack(32, 32, 9000, 12, 1.5, 40.0, 200.0, 0.3, seed=9060, pixel="u8")
+    plan = gpu.Plan(32, 32, 9000, pixel="u8", k2_max=60, method="fourier")
+    mn, full = plan.workspace_size()
+    plan.allocate_workspace(mn)
+    D = plan.structure_function(frames.cuda())
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    Do, _ = oracle_D(frames.numpy(), k2_max=60)
+    e = per_q_error(D.cpu().numpy(), Do)
+    say("32x32x9000 k2_max 60, min workspace (%d q):" % D.shape[0], describe(e), "(full ws %d, min %d)" % (full, mn))
+    assert e.max() <= TOL_F32
+    assert np.all(D[:, 0].cpu().numpy() == 0.0)
