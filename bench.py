@@ -723,17 +723,18 @@ def long_stack_leg(recipe, M, N=16384, steps=3):
 
 
 def long_stack_all_lags(recipe, frames, N, steps=3):
-    """All N lags of the same stack by the time transform of length 16384 and,
-    once, by direct differences (the comparison the paper draws between the two
-    schemes at its longest stacks); the largest per-q relative difference of
-    the two D."""
+    """All N lags of the same stack by the time transform of length 16384 (FP32
+    and FP16 spectra stores) and, once, by direct differences (the comparison
+    the paper draws between the two schemes at its longest stacks); the largest
+    per-q relative differences of the D."""
     import torch
     from paper_2012_05695_amd import api
     W, H = recipe["W"], recipe["H"]
     res, Ds = {}, {}
-    for method, reps in (("fourier", steps), ("direct", 1)):
+    for method, reps in (("fourier", steps), ("fourier_f16", steps), ("direct", 1)):
         print("bench: long stack, all %d lags, %s" % (N, method), file=sys.stderr, flush=True)
-        plan = api.Plan(W, H, N, pixel=recipe["pixel"], method=method)
+        spectrum = "f16" if method.endswith("f16") else "f32"
+        plan = api.Plan(W, H, N, pixel=recipe["pixel"], spectrum=spectrum, method=method.split("_")[0])
         plan.allocate_workspace()
         D = plan.structure_function(frames)
         torch.cuda.synchronize()
@@ -747,7 +748,7 @@ def long_stack_all_lags(recipe, frames, N, steps=3):
         plan.status()
         ms = ev[0].elapsed_time(ev[1]) / reps
         prof = {k: plan.profile(k) for k in ("step1", "row", "col", "time")}
-        name = "time" if method == "fourier" else "direct"
+        name = "direct" if method == "direct" else "time"
         per = {(name if k == "time" else k): v[0] / reps for k, v in prof.items() if v[1] > 0}
         res[method] = {"ms_per_stack": ms, "frames_per_s": N / (ms * 1e-3), "kernel_ms": per}
         plan.close()
@@ -755,6 +756,8 @@ def long_stack_all_lags(recipe, frames, N, steps=3):
     num = (Ds["fourier"].double() - Ds["direct"].double()).abs().amax(dim=1)
     den = Ds["direct"].double().amax(dim=1).clamp_min(1e-300)
     res["max_rel_diff_fourier_vs_direct"] = float((num / den).max())
+    num = (Ds["fourier_f16"].double() - Ds["fourier"].double()).abs().amax(dim=1)
+    res["max_rel_diff_fourier_f16_vs_f32"] = float((num / den).max())
     res["direct_over_fourier"] = res["direct"]["ms_per_stack"] / res["fourier"]["ms_per_stack"]
     del Ds, D
     torch.cuda.empty_cache()
